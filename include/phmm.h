@@ -1,0 +1,239 @@
+/*
+ * phmm.h — C ABI of the MI355X (gfx950) PairHMM forward library.
+ *
+ * The library computes, for every (read, haplotype) pair of a batch, the
+ * PairHMM forward likelihood log10 P(read | haplotype) of the model in
+ * Section 2 of Graca & Ilic, "Endeavor: Efficient PairHMM for Detection of
+ * DNA Variants in Genome-Scale Datasets" (HPDC '26):
+ *
+ *   eq.1  M(i,0)=I(i,0)=D(i,0)=M(0,j)=I(0,j)=0,  D(0,j) = C/k
+ *   eq.2  M(i,j) = P(r_i|h_j)(T_MM_i M(i-1,j-1) + T_IM I(i-1,j-1) + T_DM D(i-1,j-1))
+ *         I(i,j) = T_MI_i M(i-1,j) + T_II I(i-1,j)
+ *         D(i,j) = T_MD_i M(i,j-1) + T_DD D(i,j-1)
+ *   eq.3  P(r_i|h_j) = 1 - eps_i (match) or eps_i/3 (mismatch), eps_i = 10^(-Q_i/10)
+ *   eq.4  L = sum_j M(l,j) + I(l,j)
+ *
+ * evaluated in the row-level formulation of Section 3.1 (eq.5-7): a whole
+ * DP row is updated at once and the within-row Delete chain is resolved as
+ * a first-order linear recurrence by a wavefront scan (Section 3.4,
+ * Algorithm 1).
+ *
+ * Value conventions
+ *   - bases are upper-case ASCII 'A','C','G','T' or 'N'; 'N' in either
+ *     sequence matches any base;
+ *   - qualities are raw Phred bytes 0..255 (the paper's -33 is the FASTQ
+ *     character offset and is removed by the caller);
+ *     T_MI_i = 10^(-ins_i/10), T_MD_i = 10^(-del_i/10),
+ *     T_MM_i = max(0, 1 - T_MI_i - T_MD_i), g_i = 10^(-gcp_i/10),
+ *     T_II_i = T_DD_i = g_i, T_IM_i = T_DM_i = 1 - g_i
+ *     (gcp = 10 gives the paper's constants 0.1 / 0.9);
+ *   - the start row is D(0,j) = C/k for j = 0..k (also j = 0), k = haplotype
+ *     length, and the result is reported with C divided out:
+ *     out_log10 = log10 L.
+ *
+ * Memory and ownership
+ *   - the caller owns every buffer; inputs are read-only for the call;
+ *   - the synchronous entry points copy host inputs to the device, run, copy
+ *     results back and keep no pointer after they return;
+ *   - the asynchronous entry point takes device pointers, enqueues all work
+ *     on the caller's HIP stream and returns at once; every buffer must stay
+ *     alive until the stream has passed the call.
+ *
+ * Errors
+ *   - every entry point returns PHMM_OK or a negative PHMM_E* code;
+ *   - the synchronous entry points validate every input on the host before
+ *     any device work; on error nothing is written to the outputs and
+ *     phmm_last_error() names the first offending index;
+ *   - a phmm_ctx is used by one host thread at a time.
+ *
+ * There is no CPU fallback: without a usable gfx950 device every compute
+ * entry point fails with PHMM_EDEVICE.
+ */
+#ifndef PHMM_H
+#define PHMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PHMM_OK 0
+#define PHMM_EINVAL (-1)   /* null pointer, empty sequence, base not in ACGTN, offsets not
+                              monotone, index out of range, bad option                  */
+#define PHMM_ERANGE (-2)   /* read longer than PHMM_MAX_READ or haplotype longer than
+                              PHMM_MAX_HAP                                               */
+#define PHMM_ENOMEM (-3)   /* device or host allocation failed, or workspace too small   */
+#define PHMM_EDEVICE (-4)  /* HIP error, or no gfx950 device                             */
+#define PHMM_ETIMEOUT (-5) /* long-pair kernel watchdog fired                            */
+
+#define PHMM_MAX_READ 131072u
+#define PHMM_MAX_HAP (1u << 20)
+
+/* out_flags bits (one byte per pair) */
+#define PHMM_FLAG_FP32 0x01u     /* FP32 result accepted                           */
+#define PHMM_FLAG_RERUN 0x02u    /* FP32 result rejected, recomputed in FP64       */
+#define PHMM_FLAG_LONG 0x04u     /* long-pair (multi-wavefront tile) kernel        */
+#define PHMM_FLAG_RESCALED 0x08u /* power-of-two rescaling with integer exponent  */
+#define PHMM_FLAG_FP64 0x10u     /* computed in FP64                               */
+
+/* Precision policy. */
+#define PHMM_FP32_RERUN 0 /* FP32 with scale 2^120/k; pairs whose FP32 scaled sum
+                             is below accept_min_sum (or not finite) rerun in FP64 */
+#define PHMM_FP64_PLAIN 1 /* every pair in FP64 with scale 2^1020/k                 */
+
+typedef struct phmm_options {
+    int precision;          /* PHMM_FP32_RERUN (default) or PHMM_FP64_PLAIN          */
+    double accept_min_sum;  /* FP32 acceptance threshold on the scaled sum S32 =
+                               L * 2^120; default 1e-28 (log10 L >= -64.12)           */
+    int force_class;        /* -1: the packer picks columns-per-lane per region;
+                               >= 0: force this class index (see phmm_class_n)       */
+    int one_pair_per_wave;  /* 1: no packing, every pair gets its own wavefront      */
+    uint32_t fp32_max_rows; /* reads longer than this go straight to FP64 (FP32
+                               rounding bias grows with the row count); default 2048 */
+    uint32_t watchdog_spins;/* long kernel: polls of a neighbour tile before giving
+                               up with PHMM_ETIMEOUT; 0 = default                     */
+    int timing;             /* 1: record per-phase HIP events (phmm_last_timing)     */
+} phmm_options;
+
+/* Fills *opt with the defaults above. */
+void phmm_default_options(phmm_options* opt);
+
+typedef struct phmm_ctx phmm_ctx;
+
+/* Creates a context on HIP device `device` (0-based).  Owns a HIP stream,
+ * the quality->probability table in device memory and a growable device
+ * arena for the synchronous API.  opt == NULL selects the defaults.
+ * Errors: PHMM_EINVAL (out == NULL, bad option), PHMM_EDEVICE (no such
+ * device, not gfx950, HIP failure). */
+int phmm_create(phmm_ctx** out, int device, const phmm_options* opt);
+
+/* Frees everything the context owns.  NULL is ignored. */
+void phmm_destroy(phmm_ctx* ctx);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* phmm_last_error(void);
+
+/* Number of column classes and the columns-per-lane N of class c. */
+int phmm_num_classes(void);
+int phmm_class_n(int c);
+
+/*
+ * Batched forward pass (host buffers, synchronous).
+ *
+ * reads, base_quals, ins_quals, del_quals, gcp : n_bases bytes each, the
+ *     reads one after another; read r is bytes [read_offsets[r],
+ *     read_offsets[r+1]) of every one of the five arrays;
+ * read_offsets : n_reads + 1 entries, read_offsets[0] = 0, non-decreasing,
+ *     each read at least one base and at most PHMM_MAX_READ;
+ * haplotypes / hap_offsets / n_haps : the same layout for haplotypes (each
+ *     1..PHMM_MAX_HAP bases);
+ * pair_list : n_pairs (read index, haplotype index) uint32 pairs, row-major;
+ *     pairs of the same read should be adjacent (the packer groups adjacent
+ *     pairs of one read into one wavefront);
+ * out_log10 : n_pairs doubles, log10 P(read | hap);
+ * out_flags : n_pairs bytes of PHMM_FLAG_* bits, or NULL.
+ * n_pairs == 0 is valid and does nothing.
+ */
+int phmm_forward_batch(phmm_ctx* ctx,
+                       const uint8_t* reads, const uint8_t* base_quals,
+                       const uint8_t* ins_quals, const uint8_t* del_quals,
+                       const uint8_t* gcp, const uint64_t* read_offsets, uint32_t n_reads,
+                       const uint8_t* haplotypes, const uint64_t* hap_offsets,
+                       uint32_t n_haps, const uint32_t* pair_list, uint64_t n_pairs,
+                       double* out_log10, uint8_t* out_flags);
+
+/*
+ * Host-side validation of a batch exactly as phmm_forward_batch performs it
+ * (no device needed): returns PHMM_OK or the first error, with
+ * phmm_last_error() naming the offending index.  Optionally reports the
+ * longest read and haplotype.
+ */
+int phmm_validate_batch(const uint8_t* reads, const uint8_t* base_quals,
+                        const uint8_t* ins_quals, const uint8_t* del_quals,
+                        const uint8_t* gcp, const uint64_t* read_offsets, uint32_t n_reads,
+                        const uint8_t* haplotypes, const uint64_t* hap_offsets,
+                        uint32_t n_haps, const uint32_t* pair_list, uint64_t n_pairs,
+                        uint32_t* max_read_len, uint32_t* max_hap_len);
+
+/*
+ * One pair, FP64 (PHMM_FP64_PLAIN on a library-owned default context on
+ * device 0).  Arrays hold read_len resp. hap_len bytes.
+ */
+int phmm_forward_one(const uint8_t* read, const uint8_t* base_quals,
+                     const uint8_t* ins_quals, const uint8_t* del_quals,
+                     const uint8_t* gcp, uint32_t read_len, const uint8_t* hap,
+                     uint32_t hap_len, double* out_log10);
+
+/* Device-resident batch: the fields of phmm_forward_batch as device
+ * pointers, plus bounds the caller guarantees (used to size the workspace
+ * and to route pairs; they are not re-checked on the device). */
+typedef struct phmm_device_batch {
+    const uint8_t* reads;
+    const uint8_t* base_quals;
+    const uint8_t* ins_quals;
+    const uint8_t* del_quals;
+    const uint8_t* gcp;
+    const uint64_t* read_offsets;
+    uint32_t n_reads;
+    const uint8_t* haplotypes;
+    const uint64_t* hap_offsets;
+    uint32_t n_haps;
+    const uint32_t* pair_list;
+    uint64_t n_pairs;
+    uint32_t max_read_len; /* >= every read length in the batch      */
+    uint32_t max_hap_len;  /* >= every haplotype length in the batch */
+} phmm_device_batch;
+
+/* Device workspace bytes phmm_forward_batch_async needs for a batch of
+ * n_pairs pairs within the given length bounds. */
+size_t phmm_workspace_bytes(phmm_ctx* ctx, uint64_t n_pairs, uint32_t max_read_len,
+                            uint32_t max_hap_len);
+
+/*
+ * Stream-ordered forward pass over device-resident inputs: packing, FP32
+ * kernels, FP64 reruns and long pairs are all enqueued on hip_stream (a
+ * hipStream_t; NULL = the null stream) with no host synchronisation and no
+ * allocation.  d_out_log10 (n_pairs doubles) and d_flags (n_pairs bytes, or
+ * NULL) are device pointers; d_workspace holds at least
+ * phmm_workspace_bytes(...) bytes of device memory.  Only the host-visible
+ * fields of *b are checked (null pointers, bounds, workspace size); device
+ * contents are trusted.  Errors detected on the device (watchdog) are
+ * reported by phmm_device_status() after the stream has passed the call.
+ */
+int phmm_forward_batch_async(phmm_ctx* ctx, const phmm_device_batch* b, double* d_out_log10,
+                             uint8_t* d_flags, void* d_workspace, size_t ws_bytes,
+                             void* hip_stream);
+
+/* Synchronises with the stream of the last async call and returns PHMM_OK or
+ * the error the device recorded for it (PHMM_ETIMEOUT). */
+int phmm_device_status(phmm_ctx* ctx, void* d_workspace);
+
+/* Counters of the last call on a workspace (synchronises the stream). */
+typedef struct phmm_counts {
+    uint64_t packs_fp32;   /* wavefront packs run in FP32              */
+    uint64_t packs_fp64;   /* wavefront packs run in FP64 (plain mode) */
+    uint64_t rerun_items;  /* FP32 packs with at least one rerun pair  */
+    uint64_t rerun_pairs;  /* pairs recomputed in FP64                 */
+    uint64_t long_pairs;   /* pairs sent to the long-pair kernel       */
+    uint64_t long_tiles;   /* wavefront tiles of the long-pair kernel  */
+    uint64_t lane_columns; /* sum over packs of 64*N (occupied cells per row) */
+} phmm_counts;
+int phmm_last_counts(phmm_ctx* ctx, void* d_workspace, phmm_counts* out);
+
+/* Per-phase device times of the last call made with options.timing = 1
+ * (milliseconds, from HIP events on the call's stream; synchronises). */
+typedef struct phmm_timing {
+    float pack_ms;     /* grouping and packing of pairs           */
+    float short_ms;    /* short-pair kernels, FP32 or FP64 plain  */
+    float rerun_ms;    /* FP64 rerun kernels                      */
+    float long_ms;     /* long-pair kernels                       */
+    float total_ms;    /* whole call                              */
+} phmm_timing;
+int phmm_last_timing(phmm_ctx* ctx, phmm_timing* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PHMM_H */

@@ -1,0 +1,541 @@
+// Host runtime of the PairHMM forward library: contexts, validation,
+// workspace layout and the stream-ordered launch sequence behind the C ABI
+// declared in include/phmm.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "phmm.h"
+#include "phmm_internal.h"
+
+namespace phmm {
+void launch_short(bool fp32, int cls, int grid, hipStream_t s, const Batch& b, const Tables& t,
+                  const Work& w, const Policy& p);
+const void* short_kernel_ptr(bool fp32, int cls);
+__global__ void reset_kernel(Counters* c);
+__global__ void pack_plan_kernel(Batch b, Work w, Policy pol);
+__global__ void pack_layout_kernel(Counters* c);
+__global__ void pack_emit_kernel(Batch b, Work w, Policy pol);
+void launch_long(hipStream_t s, int grid, const Batch& b, const Tables& t, const Work& w,
+                 const Policy& p);
+const void* long_kernel_ptr();
+__host__ __device__ uint32_t long_slots(int grid);
+}  // namespace phmm
+
+using namespace phmm;
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(PHMM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+extern "C" const char* phmm_last_error(void) { return g_err.c_str(); }
+extern "C" int phmm_num_classes(void) { return kNumClasses; }
+extern "C" int phmm_class_n(int c) { return (c >= 0 && c < kNumClasses) ? class_n(c) : -1; }
+
+extern "C" void phmm_default_options(phmm_options* o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->precision = PHMM_FP32_RERUN;
+    o->accept_min_sum = 1e-28;
+    o->force_class = -1;
+    o->one_pair_per_wave = 0;
+    o->fp32_max_rows = 2048;
+    o->watchdog_spins = 0;
+    o->timing = 0;
+}
+
+// ---------------------------------------------------------------- context
+struct phmm_ctx {
+    int device = 0;
+    phmm_options opt{};
+    hipStream_t stream = nullptr;
+    int cus = 0;
+    int grid_short[2][kNumClasses] = {};  // [fp32?0:1] persistent wavefronts per class
+    int grid_long = 0;
+    double* d_p64 = nullptr;
+    double* d_pw64 = nullptr;
+    float* d_pw32 = nullptr;
+    double* d_pwlong = nullptr;
+    // synchronous-API arena
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    // timing
+    hipEvent_t ev[6] = {};
+    bool timed = false;
+};
+
+static Policy make_policy(const phmm_options& o)
+{
+    Policy p;
+    memset(&p, 0, sizeof p);
+    p.precision = o.precision;
+    p.force_class = o.force_class;
+    p.one_pair_per_wave = o.one_pair_per_wave;
+    p.fp32_max_rows = o.fp32_max_rows;
+    p.accept_min_sum = (float)o.accept_min_sum;
+    p.watchdog_spins = o.watchdog_spins ? o.watchdog_spins : 4000000u;
+    for (int prec = 0; prec < 2; ++prec)
+        for (int c = 0; c < kNumClasses; ++c)
+            p.cost[prec][c] = (float)class_n(c) + 3.0f;  // row cost ~ N cells + scan
+    return p;
+}
+
+static int check_options(const phmm_options& o)
+{
+    if (o.precision != PHMM_FP32_RERUN && o.precision != PHMM_FP64_PLAIN)
+        return fail(PHMM_EINVAL, "options.precision must be PHMM_FP32_RERUN or PHMM_FP64_PLAIN");
+    if (!(o.accept_min_sum > 0.0) || o.accept_min_sum > 1e30)
+        return fail(PHMM_EINVAL, "options.accept_min_sum must be in (0, 1e30]");
+    if (o.force_class < -1 || o.force_class >= kNumClasses)
+        return fail(PHMM_EINVAL, "options.force_class must be -1 or 0..%d", kNumClasses - 1);
+    return PHMM_OK;
+}
+
+static int build_tables(phmm_ctx* c)
+{
+    std::vector<double> p64(256);
+    for (int q = 0; q < 256; ++q) p64[q] = pow(10.0, -(double)q / 10.0);
+    std::vector<double> pw64((size_t)kNumClasses * 256 * kPowStride);
+    std::vector<float> pw32(pw64.size());
+    for (int cls = 0; cls < kNumClasses; ++cls) {
+        const int N = class_n(cls);
+        for (int q = 0; q < 256; ++q) {
+            double* row = &pw64[((size_t)cls * 256 + q) * kPowStride];
+            for (int m = 0; m <= 64; ++m) row[m] = pow(p64[q], (double)(N * m));
+            row[65] = pow(p64[q], (double)(N - 1));
+        }
+    }
+    for (size_t i = 0; i < pw64.size(); ++i) pw32[i] = (float)pw64[i];
+    std::vector<double> pwl((size_t)256 * kPowStride);
+    for (int q = 0; q < 256; ++q) {
+        for (int m = 0; m <= 64; ++m) pwl[(size_t)q * kPowStride + m] = pow(p64[q], (double)(kLongN * m));
+        pwl[(size_t)q * kPowStride + 65] = pow(p64[q], (double)(kLongN - 1));
+    }
+    HIP_TRY(hipMalloc(&c->d_p64, p64.size() * 8));
+    HIP_TRY(hipMalloc(&c->d_pw64, pw64.size() * 8));
+    HIP_TRY(hipMalloc(&c->d_pw32, pw32.size() * 4));
+    HIP_TRY(hipMalloc(&c->d_pwlong, pwl.size() * 8));
+    HIP_TRY(hipMemcpy(c->d_p64, p64.data(), p64.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d_pw64, pw64.data(), pw64.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d_pw32, pw32.data(), pw32.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d_pwlong, pwl.data(), pwl.size() * 8, hipMemcpyHostToDevice));
+    return PHMM_OK;
+}
+
+extern "C" void phmm_destroy(phmm_ctx* c)
+{
+    if (!c) return;
+    // best-effort teardown: errors here have nowhere to go
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->d_p64);
+    (void)hipFree(c->d_pw64);
+    (void)hipFree(c->d_pw32);
+    (void)hipFree(c->d_pwlong);
+    (void)hipFree(c->arena);
+    for (auto& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+static int create_impl(phmm_ctx* c, int device)
+{
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(PHMM_EDEVICE, "no HIP device %d (%d present)", device, ndev);
+    HIP_TRY(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(PHMM_EDEVICE, "device %d is %s; this library is built for gfx950 only", device,
+                    prop.gcnArchName);
+    c->device = device;
+    c->cus = prop.multiProcessorCount;
+    HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    for (auto& e : c->ev) HIP_TRY(hipEventCreate(&e));
+    for (int prec = 0; prec < 2; ++prec)
+        for (int cls = 0; cls < kNumClasses; ++cls) {
+            int per_cu = 0;
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, short_kernel_ptr(prec == 0, cls), kWave, 0));
+            c->grid_short[prec][cls] = std::max(1, per_cu) * c->cus;
+        }
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, long_kernel_ptr(), kWave, 0));
+    c->grid_long = std::max(1, per_cu) * c->cus;
+    return build_tables(c);
+}
+
+extern "C" int phmm_create(phmm_ctx** out, int device, const phmm_options* opt)
+{
+    if (!out) return fail(PHMM_EINVAL, "phmm_create: out is NULL");
+    *out = nullptr;
+    phmm_ctx* c = new (std::nothrow) phmm_ctx();
+    if (!c) return fail(PHMM_ENOMEM, "phmm_create: out of host memory");
+    if (opt) c->opt = *opt;
+    else phmm_default_options(&c->opt);
+    int rc = check_options(c->opt);
+    if (rc == PHMM_OK) rc = create_impl(c, device);
+    if (rc != PHMM_OK) {
+        std::string keep = g_err;
+        phmm_destroy(c);
+        g_err = keep;
+        return rc;
+    }
+    *out = c;
+    return PHMM_OK;
+}
+
+// ---------------------------------------------------------------- workspace
+struct Layout {
+    size_t ctr, chunk_info, packs, items, long_list, long_pref, ring, slot, part, total;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static Layout layout_for(const phmm_ctx* c, uint64_t n_pairs)
+{
+    Layout L;
+    size_t o = 0;
+    const uint64_t n = n_pairs ? n_pairs : 1;
+    const uint32_t slots = long_slots(c->grid_long);
+    L.ctr = o; o = align256(o + sizeof(Counters));
+    L.chunk_info = o; o = align256(o + n * 4);
+    L.packs = o; o = align256(o + n * sizeof(Pack));
+    L.items = o; o = align256(o + n * sizeof(Item));
+    L.long_list = o; o = align256(o + n * 4);
+    L.long_pref = o; o = align256(o + (n + 1) * 4);
+    L.ring = o; o = align256(o + (size_t)slots * (kRing + 1) * 4 * sizeof(double));
+    L.slot = o; o = align256(o + (size_t)slots * 3 * sizeof(uint32_t));
+    L.part = o; o = align256(o + 64);
+    L.total = o;
+    return L;
+}
+
+extern "C" size_t phmm_workspace_bytes(phmm_ctx* c, uint64_t n_pairs, uint32_t max_read_len,
+                                       uint32_t max_hap_len)
+{
+    (void)max_read_len;
+    (void)max_hap_len;
+    if (!c) return 0;
+    return layout_for(c, n_pairs).total;
+}
+
+static Work work_for(phmm_ctx* c, void* ws, uint64_t n_pairs)
+{
+    Layout L = layout_for(c, n_pairs);
+    char* base = static_cast<char*>(ws);
+    Work w;
+    w.ctr = reinterpret_cast<Counters*>(base + L.ctr);
+    w.chunk_info = reinterpret_cast<uint32_t*>(base + L.chunk_info);
+    w.packs = reinterpret_cast<Pack*>(base + L.packs);
+    w.items = reinterpret_cast<Item*>(base + L.items);
+    w.long_list = reinterpret_cast<uint32_t*>(base + L.long_list);
+    w.long_pref = reinterpret_cast<uint32_t*>(base + L.long_pref);
+    w.long_ring = reinterpret_cast<double*>(base + L.ring);
+    w.long_prog = reinterpret_cast<uint32_t*>(base + L.slot);
+    w.long_part = reinterpret_cast<double*>(base + L.part);
+    w.max_long_tiles = long_slots(c->grid_long);
+    return w;
+}
+
+// ---------------------------------------------------------------- launch
+static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s)
+{
+    const Policy pol = make_policy(c->opt);
+    Tables t;
+    t.p64 = c->d_p64;
+    t.pw64 = c->d_pw64;
+    t.pw32 = c->d_pw32;
+    t.pwlong = c->d_pwlong;
+    const Work w = work_for(c, ws, b.n_pairs);
+    const bool timed = c->opt.timing != 0;
+    if (timed) HIP_TRY(hipEventRecord(c->ev[0], s));
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, s, w.ctr);
+    if (b.n_pairs > 0) {
+        const unsigned blocks = (unsigned)((b.n_pairs + 255) / 256);
+        hipLaunchKernelGGL(pack_plan_kernel, dim3(blocks), dim3(256), 0, s, b, w, pol);
+        hipLaunchKernelGGL(pack_layout_kernel, dim3(1), dim3(64), 0, s, w.ctr);
+        hipLaunchKernelGGL(pack_emit_kernel, dim3(blocks), dim3(256), 0, s, b, w, pol);
+    }
+    if (timed) HIP_TRY(hipEventRecord(c->ev[1], s));
+    if (b.n_pairs > 0) {
+        if (pol.precision == PHMM_FP32_RERUN)
+            for (int cls = 0; cls < kNumClasses; ++cls)
+                launch_short(true, cls, c->grid_short[0][cls], s, b, t, w, pol);
+        if (timed) HIP_TRY(hipEventRecord(c->ev[2], s));
+        for (int cls = 0; cls < kNumClasses; ++cls)
+            launch_short(false, cls, c->grid_short[1][cls], s, b, t, w, pol);
+        if (timed) HIP_TRY(hipEventRecord(c->ev[3], s));
+        launch_long(s, c->grid_long, b, t, w, pol);
+    } else if (timed) {
+        HIP_TRY(hipEventRecord(c->ev[2], s));
+        HIP_TRY(hipEventRecord(c->ev[3], s));
+    }
+    if (timed) HIP_TRY(hipEventRecord(c->ev[4], s));
+    HIP_TRY(hipGetLastError());
+    c->timed = timed;
+    return PHMM_OK;
+}
+
+extern "C" int phmm_forward_batch_async(phmm_ctx* c, const phmm_device_batch* db, double* d_out,
+                                        uint8_t* d_flags, void* d_ws, size_t ws_bytes,
+                                        void* hip_stream)
+{
+    if (!c || !db) return fail(PHMM_EINVAL, "phmm_forward_batch_async: ctx or batch is NULL");
+    if (db->n_pairs > 0xffffffffull) return fail(PHMM_ERANGE, "n_pairs exceeds 2^32-1");
+    if (db->n_pairs > 0 && (!db->reads || !db->base_quals || !db->ins_quals || !db->del_quals ||
+                            !db->gcp || !db->read_offsets || !db->haplotypes ||
+                            !db->hap_offsets || !db->pair_list || !d_out || !d_ws))
+        return fail(PHMM_EINVAL, "phmm_forward_batch_async: NULL device pointer");
+    if (db->max_read_len > PHMM_MAX_READ)
+        return fail(PHMM_ERANGE, "max_read_len %u exceeds %u", db->max_read_len, PHMM_MAX_READ);
+    if (db->max_hap_len > PHMM_MAX_HAP)
+        return fail(PHMM_ERANGE, "max_hap_len %u exceeds %u", db->max_hap_len, PHMM_MAX_HAP);
+    const size_t need = phmm_workspace_bytes(c, db->n_pairs, db->max_read_len, db->max_hap_len);
+    if (ws_bytes < need) return fail(PHMM_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    HIP_TRY(hipSetDevice(c->device));
+    Batch b;
+    b.reads = db->reads;
+    b.bq = db->base_quals;
+    b.iq = db->ins_quals;
+    b.dq = db->del_quals;
+    b.gq = db->gcp;
+    b.read_off = db->read_offsets;
+    b.haps = db->haplotypes;
+    b.hap_off = db->hap_offsets;
+    b.pairs = db->pair_list;
+    b.n_pairs = db->n_pairs;
+    b.out = d_out;
+    b.flags = d_flags;
+    return enqueue(c, b, d_ws, static_cast<hipStream_t>(hip_stream));
+}
+
+extern "C" int phmm_device_status(phmm_ctx* c, void* d_ws)
+{
+    if (!c || !d_ws) return fail(PHMM_EINVAL, "phmm_device_status: NULL argument");
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipDeviceSynchronize());
+    Counters h;
+    HIP_TRY(hipMemcpy(&h, d_ws, sizeof h, hipMemcpyDeviceToHost));
+    if (h.status != 0) return fail((int)h.status, "device reported error %d", (int)h.status);
+    return PHMM_OK;
+}
+
+extern "C" int phmm_last_counts(phmm_ctx* c, void* d_ws, phmm_counts* out)
+{
+    if (!c || !d_ws || !out) return fail(PHMM_EINVAL, "phmm_last_counts: NULL argument");
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipDeviceSynchronize());
+    Counters h;
+    HIP_TRY(hipMemcpy(&h, d_ws, sizeof h, hipMemcpyDeviceToHost));
+    memset(out, 0, sizeof *out);
+    for (int k = 0; k < kNumClasses; ++k) {
+        out->packs_fp32 += h.pack_cnt[0][k];
+        out->packs_fp64 += h.pack_cnt[1][k];
+    }
+    out->rerun_items = h.rerun_items;
+    out->rerun_pairs = h.rerun_pairs;
+    out->long_pairs = h.n_long;
+    out->long_tiles = h.long_tiles;
+    out->lane_columns = h.lane_columns;
+    return PHMM_OK;
+}
+
+extern "C" int phmm_last_timing(phmm_ctx* c, phmm_timing* out)
+{
+    if (!c || !out) return fail(PHMM_EINVAL, "phmm_last_timing: NULL argument");
+    if (!c->timed) return fail(PHMM_EINVAL, "phmm_last_timing: last call was not timed");
+    HIP_TRY(hipEventSynchronize(c->ev[4]));
+    HIP_TRY(hipEventElapsedTime(&out->pack_ms, c->ev[0], c->ev[1]));
+    HIP_TRY(hipEventElapsedTime(&out->short_ms, c->ev[1], c->ev[2]));
+    HIP_TRY(hipEventElapsedTime(&out->rerun_ms, c->ev[2], c->ev[3]));
+    HIP_TRY(hipEventElapsedTime(&out->long_ms, c->ev[3], c->ev[4]));
+    HIP_TRY(hipEventElapsedTime(&out->total_ms, c->ev[0], c->ev[4]));
+    return PHMM_OK;
+}
+
+// ---------------------------------------------------------------- validation
+static bool is_base(uint8_t x) { return x == 'A' || x == 'C' || x == 'G' || x == 'T' || x == 'N'; }
+
+static int validate(const uint8_t* reads, const uint8_t* bq, const uint8_t* iq, const uint8_t* dq,
+                    const uint8_t* gq, const uint64_t* ro, uint32_t n_reads, const uint8_t* haps,
+                    const uint64_t* ho, uint32_t n_haps, const uint32_t* pl, uint64_t n_pairs,
+                    double* out, uint32_t* max_l, uint32_t* max_k)
+{
+    *max_l = 0;
+    *max_k = 0;
+    if (n_pairs == 0) return PHMM_OK;
+    if (!ro || !ho || !pl || !out) return fail(PHMM_EINVAL, "NULL offsets, pair_list or output");
+    if (n_reads == 0 || n_haps == 0) return fail(PHMM_EINVAL, "pairs given but no reads or haplotypes");
+    if (!reads || !bq || !iq || !dq || !gq || !haps) return fail(PHMM_EINVAL, "NULL sequence or quality array");
+    if (ro[0] != 0) return fail(PHMM_EINVAL, "read_offsets[0] = %llu, must be 0", (unsigned long long)ro[0]);
+    if (ho[0] != 0) return fail(PHMM_EINVAL, "hap_offsets[0] = %llu, must be 0", (unsigned long long)ho[0]);
+    for (uint32_t r = 0; r < n_reads; ++r) {
+        if (ro[r + 1] <= ro[r]) return fail(PHMM_EINVAL, "read %u is empty or offsets not increasing", r);
+        uint64_t len = ro[r + 1] - ro[r];
+        if (len > PHMM_MAX_READ) return fail(PHMM_ERANGE, "read %u has %llu bases (max %u)", r, (unsigned long long)len, PHMM_MAX_READ);
+        if (len > *max_l) *max_l = (uint32_t)len;
+    }
+    for (uint32_t h = 0; h < n_haps; ++h) {
+        if (ho[h + 1] <= ho[h]) return fail(PHMM_EINVAL, "haplotype %u is empty or offsets not increasing", h);
+        uint64_t len = ho[h + 1] - ho[h];
+        if (len > PHMM_MAX_HAP) return fail(PHMM_ERANGE, "haplotype %u has %llu bases (max %u)", h, (unsigned long long)len, PHMM_MAX_HAP);
+        if (len > *max_k) *max_k = (uint32_t)len;
+    }
+    const uint64_t nb = ro[n_reads], nh = ho[n_haps];
+    for (uint64_t i = 0; i < nb; ++i)
+        if (!is_base(reads[i])) return fail(PHMM_EINVAL, "read base %llu is 0x%02x, not one of ACGTN", (unsigned long long)i, reads[i]);
+    for (uint64_t i = 0; i < nh; ++i)
+        if (!is_base(haps[i])) return fail(PHMM_EINVAL, "haplotype base %llu is 0x%02x, not one of ACGTN", (unsigned long long)i, haps[i]);
+    for (uint64_t p = 0; p < n_pairs; ++p) {
+        if (pl[2 * p] >= n_reads) return fail(PHMM_EINVAL, "pair %llu: read index %u >= %u", (unsigned long long)p, pl[2 * p], n_reads);
+        if (pl[2 * p + 1] >= n_haps) return fail(PHMM_EINVAL, "pair %llu: haplotype index %u >= %u", (unsigned long long)p, pl[2 * p + 1], n_haps);
+    }
+    return PHMM_OK;
+}
+
+extern "C" int phmm_validate_batch(const uint8_t* reads, const uint8_t* bq, const uint8_t* iq,
+                                   const uint8_t* dq, const uint8_t* gq, const uint64_t* ro,
+                                   uint32_t n_reads, const uint8_t* haps, const uint64_t* ho,
+                                   uint32_t n_haps, const uint32_t* pl, uint64_t n_pairs,
+                                   uint32_t* max_read_len, uint32_t* max_hap_len)
+{
+    uint32_t ml = 0, mk = 0;
+    double dummy = 0.0;
+    if (n_pairs > 0xffffffffull) return fail(PHMM_ERANGE, "n_pairs exceeds 2^32-1");
+    int rc = validate(reads, bq, iq, dq, gq, ro, n_reads, haps, ho, n_haps, pl, n_pairs, &dummy,
+                      &ml, &mk);
+    if (max_read_len) *max_read_len = ml;
+    if (max_hap_len) *max_hap_len = mk;
+    return rc;
+}
+
+static int ensure_arena(phmm_ctx* c, size_t bytes)
+{
+    if (c->arena_bytes >= bytes) return PHMM_OK;
+    if (c->arena) {
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        HIP_TRY(hipFree(c->arena));
+        c->arena = nullptr;
+        c->arena_bytes = 0;
+    }
+    size_t sz = std::max(bytes, c->arena_bytes * 3 / 2);
+    if (hipMalloc(&c->arena, sz) != hipSuccess) {
+        c->arena = nullptr;
+        return fail(PHMM_ENOMEM, "device arena of %zu bytes", sz);
+    }
+    c->arena_bytes = sz;
+    return PHMM_OK;
+}
+
+extern "C" int phmm_forward_batch(phmm_ctx* c, const uint8_t* reads, const uint8_t* bq,
+                                  const uint8_t* iq, const uint8_t* dq, const uint8_t* gq,
+                                  const uint64_t* ro, uint32_t n_reads, const uint8_t* haps,
+                                  const uint64_t* ho, uint32_t n_haps, const uint32_t* pl,
+                                  uint64_t n_pairs, double* out, uint8_t* flags)
+{
+    if (!c) return fail(PHMM_EINVAL, "phmm_forward_batch: ctx is NULL");
+    if (n_pairs > 0xffffffffull) return fail(PHMM_ERANGE, "n_pairs exceeds 2^32-1");
+    uint32_t max_l, max_k;
+    int rc = validate(reads, bq, iq, dq, gq, ro, n_reads, haps, ho, n_haps, pl, n_pairs, out,
+                      &max_l, &max_k);
+    if (rc != PHMM_OK || n_pairs == 0) return rc;
+    HIP_TRY(hipSetDevice(c->device));
+    const uint64_t nb = ro[n_reads], nh = ho[n_haps];
+    size_t o = 0;
+    const size_t o_reads = o; o = align256(o + nb * 5);
+    const size_t o_ro = o; o = align256(o + ((size_t)n_reads + 1) * 8);
+    const size_t o_haps = o; o = align256(o + nh);
+    const size_t o_ho = o; o = align256(o + ((size_t)n_haps + 1) * 8);
+    const size_t o_pl = o; o = align256(o + n_pairs * 8);
+    const size_t o_out = o; o = align256(o + n_pairs * 8);
+    const size_t o_fl = o; o = align256(o + n_pairs);
+    const size_t o_ws = o;
+    const size_t ws = phmm_workspace_bytes(c, n_pairs, max_l, max_k);
+    o += ws;
+    rc = ensure_arena(c, o);
+    if (rc != PHMM_OK) return rc;
+    char* A = static_cast<char*>(c->arena);
+    hipStream_t s = c->stream;
+    HIP_TRY(hipMemcpyAsync(A + o_reads, reads, nb, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(A + o_reads + nb, bq, nb, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(A + o_reads + 2 * nb, iq, nb, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(A + o_reads + 3 * nb, dq, nb, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(A + o_reads + 4 * nb, gq, nb, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(A + o_ro, ro, ((size_t)n_reads + 1) * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(A + o_haps, haps, nh, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(A + o_ho, ho, ((size_t)n_haps + 1) * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(A + o_pl, pl, n_pairs * 8, hipMemcpyHostToDevice, s));
+    Batch b;
+    b.reads = reinterpret_cast<const uint8_t*>(A + o_reads);
+    b.bq = b.reads + nb;
+    b.iq = b.reads + 2 * nb;
+    b.dq = b.reads + 3 * nb;
+    b.gq = b.reads + 4 * nb;
+    b.read_off = reinterpret_cast<const uint64_t*>(A + o_ro);
+    b.haps = reinterpret_cast<const uint8_t*>(A + o_haps);
+    b.hap_off = reinterpret_cast<const uint64_t*>(A + o_ho);
+    b.pairs = reinterpret_cast<const uint32_t*>(A + o_pl);
+    b.n_pairs = n_pairs;
+    b.out = reinterpret_cast<double*>(A + o_out);
+    b.flags = reinterpret_cast<uint8_t*>(A + o_fl);
+    rc = enqueue(c, b, A + o_ws, s);
+    if (rc != PHMM_OK) return rc;
+    Counters h;
+    HIP_TRY(hipMemcpyAsync(&h, A + o_ws, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(out, b.out, n_pairs * 8, hipMemcpyDeviceToHost, s));
+    if (flags) HIP_TRY(hipMemcpyAsync(flags, b.flags, n_pairs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h.status != 0) return fail((int)h.status, "device reported error %d", (int)h.status);
+    return PHMM_OK;
+}
+
+static std::mutex g_default_mu;
+static phmm_ctx* g_default = nullptr;
+
+extern "C" int phmm_forward_one(const uint8_t* read, const uint8_t* bq, const uint8_t* iq,
+                                const uint8_t* dq, const uint8_t* gq, uint32_t read_len,
+                                const uint8_t* hap, uint32_t hap_len, double* out_log10)
+{
+    if (!read || !bq || !iq || !dq || !gq || !hap || !out_log10)
+        return fail(PHMM_EINVAL, "phmm_forward_one: NULL argument");
+    if (read_len == 0 || hap_len == 0) return fail(PHMM_EINVAL, "phmm_forward_one: empty sequence");
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    if (!g_default) {
+        phmm_options o;
+        phmm_default_options(&o);
+        o.precision = PHMM_FP64_PLAIN;
+        int rc = phmm_create(&g_default, 0, &o);
+        if (rc != PHMM_OK) return rc;
+    }
+    const uint64_t ro[2] = {0, read_len}, ho[2] = {0, hap_len};
+    const uint32_t pl[2] = {0, 0};
+    return phmm_forward_batch(g_default, read, bq, iq, dq, gq, ro, 1, hap, ho, 1, pl, 1,
+                              out_log10, nullptr);
+}

@@ -1,0 +1,111 @@
+// Internal definitions shared by the host runtime and the gfx950 kernels of
+// the PairHMM forward library.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace phmm {
+
+// Column classes: a class fixes N, the number of consecutive haplotype
+// columns each lane of a wavefront owns in the row-level formulation
+// (paper Section 3.2: "each individual thread reads N characters from the
+// haplotype and calculates N elements of a M and I row").  A pair of
+// haplotype length k occupies ceil(k / N) lanes; pairs of one read are packed
+// side by side into one 64-lane wavefront.
+constexpr int kNumClasses = 11;
+__host__ __device__ constexpr int class_n(int c)
+{
+    return c == 0 ? 4 : c == 1 ? 6 : c == 2 ? 8 : c == 3 ? 10 : c == 4 ? 12 : c == 5 ? 14
+         : c == 6 ? 16 : c == 7 ? 18 : c == 8 ? 20 : c == 9 ? 22 : 24;
+}
+constexpr int kMaxN = 24;
+constexpr int kWave = 64;
+constexpr uint32_t kShortMaxCols = kWave * kMaxN;  // longer haplotypes use the long kernel
+constexpr int kMaxPairsPerPack = 32;                // pair mask is 32 bits
+constexpr int kChunk = 256;                         // pairs walked by one packer thread
+
+// Power table: for class c and gap-continuation Phred byte q, entry m
+// (0..64) holds g^(N*m) with g = 10^(-q/10); entry 65 holds g^(N-1).
+constexpr int kPowStride = 66;
+
+// Long-pair kernel geometry: one wavefront per tile of kLongN * 64 columns.
+constexpr int kLongN = 16;
+constexpr int kLongTile = kLongN * kWave;
+constexpr int kRing = 512;  // rows of boundary records buffered per tile
+
+struct Pack {
+    uint32_t pair_start;  // first pair (index into pair_list)
+    uint32_t npairs;      // consecutive pairs, all of the same read
+};
+
+struct Item {             // FP64 work item: a pack and the subset of its pairs
+    uint32_t pack;        // global pack index
+    uint32_t mask;        // bit s: pair pair_start + s is computed
+};
+
+// Device counters of one call (lives at the start of the workspace).
+struct Counters {
+    uint32_t pack_cnt[2][kNumClasses];   // [0] = FP32 packs, [1] = FP64 packs
+    uint32_t pack_base[2][kNumClasses];
+    uint32_t pack_fill[2][kNumClasses];
+    uint32_t item_base[kNumClasses];
+    uint32_t item_cnt[kNumClasses];      // FP64 items: plain packs, then reruns
+    uint32_t cursor32[kNumClasses];
+    uint32_t cursor64[kNumClasses];
+    uint32_t n_long;
+    uint32_t long_tiles;
+    uint32_t long_cursor;
+    uint32_t status;                     // 0 or a PHMM_E* code (as uint32)
+    uint32_t rerun_items;
+    uint32_t rerun_pairs;
+    unsigned long long lane_columns;
+};
+
+// Everything a kernel needs to find inputs and outputs.
+struct Batch {
+    const uint8_t* reads;
+    const uint8_t* bq;
+    const uint8_t* iq;
+    const uint8_t* dq;
+    const uint8_t* gq;
+    const uint64_t* read_off;
+    const uint8_t* haps;
+    const uint64_t* hap_off;
+    const uint32_t* pairs;
+    uint64_t n_pairs;
+    double* out;
+    uint8_t* flags;
+};
+
+struct Tables {
+    const double* p64;     // 10^(-q/10), q = 0..255
+    const double* pw64;    // kNumClasses x 256 x kPowStride
+    const float* pw32;     // same, rounded to FP32
+    const double* pwlong;  // 256 x kPowStride for N = kLongN (FP64)
+};
+
+struct Work {
+    Counters* ctr;
+    uint32_t* chunk_info;  // per pair (chunk starts only)
+    Pack* packs;           // pack array, segments per (precision, class)
+    Item* items;           // FP64 items, segments per class
+    uint32_t* long_list;   // long pair indices
+    uint32_t* long_pref;   // n_long + 1 tile prefix
+    double* long_ring;     // per tile: kRing x 4 doubles
+    uint32_t* long_prog;   // per tile: rows consumed by the next tile
+    double* long_part;     // per tile: partial sum, exponent
+    uint32_t max_long_tiles;
+};
+
+struct Policy {
+    int precision;          // 0 FP32+rerun, 1 FP64 plain
+    int force_class;        // -1 or class index
+    int one_pair_per_wave;
+    uint32_t fp32_max_rows;
+    float accept_min_sum;
+    uint32_t watchdog_spins;
+    float cost[2][kNumClasses];  // relative cost of one wavefront-row per class
+};
+
+}  // namespace phmm

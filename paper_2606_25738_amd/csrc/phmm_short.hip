@@ -1,0 +1,362 @@
+// Short-pair PairHMM forward kernel for gfx950: one wavefront per pack (one
+// read against up to 32 haplotypes laid side by side over the 64 lanes).
+//
+// Row-level formulation (paper Section 3.1, eq.5-7).  For read row i the
+// whole row of M and I is computed from row i-1 only; the Delete row is not
+// stored.  With S(i,j) = sum_{b<=j} T_DD^(j-b) M(i,b) (the unrolled delete
+// chain of eq.6, so that D(i,j) = T_MD_i S(i,j-1)):
+//
+//   M(i,j) = P(r_i|h_j) (T_MM_i M(i-1,j-1) + T_IM_i I(i-1,j-1)
+//                        + T_DM_i T_MD_{i-1} S(i-1,j-2))
+//   I(i,j) = T_MI_i M(i-1,j) + T_II_i I(i-1,j)
+//
+// Lane L of a pair's segment owns the N consecutive columns c0+1..c0+N
+// (c0 = N * (L - segment start)).  Within a lane S(i-1, .) is rebuilt on the
+// fly by a one-FMA-per-column chain started from the lane's carry
+// C = S(i-1, c0-1); the carries of all lanes come from one segmented
+// first-order linear scan per row over the lanes' weighted window sums
+// (paper Section 3.4, Algorithm 1), done with DPP row shifts and row
+// broadcasts.  The window of a lane is shifted one column left (it covers
+// columns c0..c0+N-1, the first being the left neighbour's last column), so
+// the scan yields exactly the exclusive prefix S(i, c0-1) each lane needs and
+// no division by T_DD (the paper's T_DD^-1 (T - V) step) is required.
+//
+// Emission (eq.3): every pack holds one read, so r_i is wavefront-uniform.
+// Haplotype columns are held as floats whose IEEE class names the base; one
+// class test against the row's class mask selects pm = 1 - eps or
+// px = eps / 3 for each column, with 'N' on either side matching any base.
+//
+// Scale: D(0,j) = C0/k with C0 = 2^120 (FP32) or 2^1020 (FP64), eq.1.  The
+// FP32 instantiation tests each result against the acceptance threshold and
+// queues rejected pairs for the FP64 instantiation (precision policy).
+#include "phmm_dev.h"
+
+namespace phmm {
+
+template <typename R>
+struct RowRec {
+    R dp, px, tmm, tim, cd, tmi, tii, pm;
+};
+
+template <typename R>
+struct ScaleOf;
+template <>
+struct ScaleOf<float> {
+    static constexpr int exp = 120;
+};
+template <>
+struct ScaleOf<double> {
+    static constexpr int exp = 1020;
+};
+
+template <typename R>
+__device__ __forceinline__ const R* pow_table(const Tables& t, int cls, int gcp);
+template <>
+__device__ __forceinline__ const float* pow_table<float>(const Tables& t, int cls, int gcp)
+{
+    return t.pw32 + ((size_t)cls * 256 + gcp) * kPowStride;
+}
+template <>
+__device__ __forceinline__ const double* pow_table<double>(const Tables& t, int cls, int gcp)
+{
+    return t.pw64 + ((size_t)cls * 256 + gcp) * kPowStride;
+}
+
+// Row 1: M(1,j) = P(r_1|h_j) T_DM_1 C0/k, I(1,j) = 0.
+template <typename R, int N>
+__device__ __forceinline__ void row_first(R (&Mp)[N], R (&Ip)[N], const float (&hv)[N], int cmask,
+                                          const RowRec<R>& c, R minit, R g, R& Vp)
+{
+    R V = (R)0;
+    const R base = c.tim * minit;  // T_DM_1 = T_IM_1
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const R p = col_match(hv[n], cmask) ? c.pm : c.px;
+        const R m = p * base;
+        Mp[n] = m;
+        Ip[n] = (R)0;
+        if (n < N - 1) V = fmaR(g, V, m);
+    }
+    Vp = V;
+}
+
+// Rows 2..l of the row-level recurrence (see the file comment).
+template <typename R, int N>
+__device__ __forceinline__ void row_step(R (&Mp)[N], R (&Ip)[N], const float (&hv)[N], int cmask,
+                                         const RowRec<R>& c, R Mleft, R Ileft, R C, R gprev,
+                                         R gcur, R& Vp)
+{
+    R T = C, mprev = Mleft, iprev = Ileft, V = (R)0;
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const R p = col_match(hv[n], cmask) ? c.pm : c.px;
+        const R x = fmaR(c.cd, T, fmaR(c.tim, iprev, c.tmm * mprev));
+        const R m = p * x;
+        const R in = fmaR(c.tii, Ip[n], c.tmi * Mp[n]);
+        T = fmaR(gprev, T, mprev);
+        mprev = Mp[n];
+        iprev = Ip[n];
+        Mp[n] = m;
+        Ip[n] = in;
+        if (n < N - 1) V = fmaR(gcur, V, m);
+    }
+    Vp = V;
+}
+
+// FP32 instantiation: walks the FP32 packs of class CLS and queues rejected
+// pairs as FP64 items.  FP64 instantiation: walks the FP64 items of class
+// CLS (plain packs first, then reruns).
+template <typename R, int CLS>
+__global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Policy pol)
+{
+    constexpr int N = class_n(CLS);
+    constexpr bool kFP32 = sizeof(R) == 4;
+    __shared__ RowRec<R> rec[kWave];
+    __shared__ int rinfo[kWave];  // read-base class mask | gcp byte << 16
+    __shared__ int sflag[kWave];
+    __shared__ uint32_t srej;
+
+    const int lane = (int)threadIdx.x;
+    Counters* ctr = w.ctr;
+    uint32_t* cursor = kFP32 ? &ctr->cursor32[CLS] : &ctr->cursor64[CLS];
+    const uint32_t count = kFP32 ? ctr->pack_cnt[0][CLS] : ctr->item_cnt[CLS];
+    const uint32_t n_plain = ctr->pack_cnt[1][CLS];
+
+    for (;;) {
+        uint32_t it = 0;
+        if (lane == 0) it = atomicAdd(cursor, 1u);
+        it = wave_broadcast0(it);
+        if (it >= count) break;
+
+        uint32_t pack_gi, mask;
+        if (kFP32) {
+            pack_gi = ctr->pack_base[0][CLS] + it;
+            const uint32_t np = w.packs[pack_gi].npairs;
+            mask = np == 32 ? 0xffffffffu : ((1u << np) - 1u);
+        } else {
+            const Item itm = w.items[ctr->item_base[CLS] + it];
+            pack_gi = itm.pack;
+            mask = itm.mask;
+        }
+        const uint32_t pair0 = w.packs[pack_gi].pair_start;
+        pack_gi = wave_broadcast0(pack_gi);
+        mask = wave_broadcast0(mask);
+        const bool rerun_item = !kFP32 && it >= n_plain;
+
+        // ---- segment layout: lanes [start_s, start_s + ceil(k_s/N)) per pair s
+        const int nseg = __builtin_popcount(mask);
+        uint32_t my_pair = 0, my_k = 0, my_off = 0;
+        uint64_t my_h = 0;
+        int s_lanes = 0;
+        if (lane < nseg) {
+            uint32_t m = mask;
+            for (int q = 0; q < lane; ++q) m &= m - 1u;
+            my_off = (uint32_t)__builtin_ctz(m);
+            my_pair = pair0 + my_off;
+            const uint32_t h = b.pairs[2 * (uint64_t)my_pair + 1];
+            my_h = b.hap_off[h];
+            my_k = (uint32_t)(b.hap_off[h + 1] - my_h);
+            s_lanes = (int)((my_k + N - 1) / N);
+        }
+        const int incl = wave_incl_sum(s_lanes);
+        const int my_start = incl - s_lanes;
+        const int total = __builtin_amdgcn_readlane(incl, 63);
+        sflag[lane] = 0;
+        __syncthreads();
+        if (lane < nseg && my_start < kWave) sflag[my_start] = 1;
+        if (lane == 0 && total < kWave) sflag[total] = 1;
+        __syncthreads();
+        const uint64_t starts = __ballot(sflag[lane] != 0);
+        const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        const int segstart = 63 - __builtin_clzll(starts & upto);
+        const int seg = __builtin_popcountll(starts & upto) - 1;
+        const bool real = seg < nseg;
+        const int src = real ? seg : 0;
+        const uint32_t k = real ? (uint32_t)__shfl((int)my_k, src) : 1u;
+        const uint32_t hlo = (uint32_t)__shfl((int)(uint32_t)my_h, src);
+        const uint32_t hhi = (uint32_t)__shfl((int)(uint32_t)(my_h >> 32), src);
+        const uint64_t hoff = ((uint64_t)hhi << 32) | hlo;
+        const uint32_t pair = (uint32_t)__shfl((int)my_pair, src);
+        const uint32_t off = (uint32_t)__shfl((int)my_off, src);
+        const int seglanes = (int)((k + N - 1) / N);
+        const int c0 = N * (lane - segstart);
+        const bool segend = real && (lane == segstart + seglanes - 1);
+
+        // ---- haplotype columns as class-coded floats (see hap_class_value)
+        float hv[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const uint32_t j = (uint32_t)(c0 + n);
+            hv[n] = (real && j < k) ? hap_class_value(b.haps[hoff + j]) : hap_pad_value();
+        }
+
+        // ---- read and its gap-continuation profile
+        const uint32_t r = b.pairs[2 * (uint64_t)pair0];
+        const uint64_t roff = b.read_off[r];
+        const int l = (int)(b.read_off[r + 1] - roff);
+        const int g0 = b.gq[roff];
+        bool varying = false;
+        for (int i0 = 0; i0 < l; i0 += kWave) {
+            const int i = i0 + lane;
+            const bool d = i < l && (int)b.gq[roff + i] != g0;
+            if (__ballot(d) != 0ull) { varying = true; break; }
+        }
+        const R notstart = (lane != segstart) ? (R)1 : (R)0;
+        const R minit = real ? (R)(ldexp(1.0, ScaleOf<R>::exp) / (double)k) : (R)0;
+        const R* pw = pow_table<R>(t, CLS, g0);
+        ScanMul<R> mul = make_scan_mul<R>(pw, lane, segstart);
+        R gcur = (R)t.p64[g0], gprev = gcur, gN1 = pw[65];
+
+        R Mp[N], Ip[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) { Mp[n] = (R)0; Ip[n] = (R)0; }
+        R Mleft = (R)0, Ileft = (R)0, C = (R)0;
+
+        for (int i0 = 0; i0 < l; i0 += kWave) {
+            __syncthreads();
+            {   // priors of rows i0 .. i0+63 (eq.3 and the transition priors)
+                const int i = i0 + lane;
+                if (i < l) {
+                    const uint64_t a = roff + (uint64_t)i;
+                    const double eps = t.p64[b.bq[a]];
+                    const double tmi = t.p64[b.iq[a]];
+                    const double tmd_prev = i > 0 ? t.p64[b.dq[a - 1]] : 0.0;
+                    const int gc = b.gq[a];
+                    const double g = t.p64[gc];
+                    const double tmd = t.p64[b.dq[a]];
+                    double tmm = 1.0 - (tmi + tmd);
+                    tmm = tmm < 0.0 ? 0.0 : tmm;
+                    const double pm = 1.0 - eps, px = eps / 3.0, tim = 1.0 - g;
+                    RowRec<R> rr;
+                    rr.dp = (R)(pm - px);
+                    rr.px = (R)px;
+                    rr.tmm = (R)tmm;
+                    rr.tim = (R)tim;
+                    rr.cd = (R)(tim * tmd_prev);
+                    rr.tmi = (R)tmi;
+                    rr.tii = (R)g;
+                    rr.pm = (R)pm;
+                    rec[lane] = rr;
+                    rinfo[lane] = read_class_mask(b.reads[a]) | (gc << 16);
+                }
+            }
+            __syncthreads();
+            const int nrows = l - i0 < kWave ? l - i0 : kWave;
+            for (int tt = 0; tt < nrows; ++tt) {
+                const RowRec<R> c = rec[tt];
+                const int info = __builtin_amdgcn_readfirstlane(rinfo[tt]);
+                if (varying) {
+                    const int gc = info >> 16;
+                    gprev = gcur;
+                    gcur = (R)t.p64[gc];
+                    const R* pwi = pow_table<R>(t, CLS, gc);
+                    mul = make_scan_mul<R>(pwi, lane, segstart);
+                    gN1 = pwi[65];
+                }
+                const int cmask = info & 0xffff;
+                R Vp;
+                if (i0 + tt == 0)
+                    row_first<R, N>(Mp, Ip, hv, cmask, c, minit, gcur, Vp);
+                else
+                    row_step<R, N>(Mp, Ip, hv, cmask, c, Mleft, Ileft, C, gprev, gcur, Vp);
+                // carries for the next row: left neighbour's last column, and
+                // the exclusive scan of the shifted window sums
+                Mleft = notstart * dpp<kWaveShr1>(Mp[N - 1]);
+                Ileft = notstart * dpp<kWaveShr1>(Ip[N - 1]);
+                const R vsh = fmaR(gN1, Mleft, Vp);
+                C = seg_scan(notstart * dpp<kWaveShr1>(vsh), mul);
+            }
+        }
+
+        // ---- eq.4: S = sum_j M(l,j) + I(l,j) over the real columns
+        R s = (R)0;
+#pragma unroll
+        for (int n = 0; n < N; ++n)
+            if ((uint32_t)(c0 + n) < k) s += Mp[n] + Ip[n];
+        if (!real) s = (R)0;
+        s = seg_scan(s, make_sum_mul<R>(lane, segstart));
+
+        bool reject = false;
+        if (segend) {
+            const double S = (double)s;
+            if (kFP32) {
+                reject = !(S >= (double)pol.accept_min_sum) || !(S < 3.0e38);
+                if (!reject) {
+                    b.out[pair] = log10_scaled(S, ScaleOf<R>::exp);
+                    if (b.flags) b.flags[pair] = 0x01;  // FP32 accepted
+                }
+            } else {
+                // FP64 scaled sums this small would have lost bits to
+                // underflow: hand the pair to the rescaling long-pair kernel.
+                if (!(S >= 1e-290)) {
+                    const uint32_t idx = atomicAdd(&ctr->n_long, 1u);
+                    w.long_list[idx] = pair;
+                } else {
+                    b.out[pair] = log10_scaled(S, ScaleOf<R>::exp);
+                    if (b.flags) b.flags[pair] = rerun_item ? (0x02 | 0x10) : 0x10;
+                }
+            }
+        }
+        if (kFP32) {
+            if (lane == 0) srej = 0u;
+            __syncthreads();
+            if (reject) atomicOr(&srej, 1u << off);
+            __syncthreads();
+            const uint32_t rm = srej;
+            if (lane == 0 && rm != 0u) {
+                const uint32_t idx = atomicAdd(&ctr->item_cnt[CLS], 1u);
+                w.items[ctr->item_base[CLS] + idx].pack = pack_gi;
+                w.items[ctr->item_base[CLS] + idx].mask = rm;
+                atomicAdd(&ctr->rerun_items, 1u);
+                atomicAdd(&ctr->rerun_pairs, (uint32_t)__builtin_popcount(rm));
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename R, int CLS>
+static void launch_one(int cls, dim3 grid, hipStream_t s, const Batch& b, const Tables& t,
+                       const Work& w, const Policy& p)
+{
+    if (cls == CLS) hipLaunchKernelGGL((short_kernel<R, CLS>), grid, dim3(kWave), 0, s, b, t, w, p);
+}
+
+template <typename R, int... CLS>
+static void launch_dispatch(int cls, dim3 grid, hipStream_t s, const Batch& b, const Tables& t,
+                            const Work& w, const Policy& p, std::integer_sequence<int, CLS...>)
+{
+    (launch_one<R, CLS>(cls, grid, s, b, t, w, p), ...);
+}
+
+void launch_short(bool fp32, int cls, int grid, hipStream_t s, const Batch& b, const Tables& t,
+                  const Work& w, const Policy& p)
+{
+    if (fp32)
+        launch_dispatch<float>(cls, dim3(grid), s, b, t, w, p,
+                               std::make_integer_sequence<int, kNumClasses>{});
+    else
+        launch_dispatch<double>(cls, dim3(grid), s, b, t, w, p,
+                                std::make_integer_sequence<int, kNumClasses>{});
+}
+
+template <typename R, int CLS>
+static const void* kernel_ptr_one(int cls)
+{
+    return cls == CLS ? reinterpret_cast<const void*>(&short_kernel<R, CLS>) : nullptr;
+}
+template <typename R, int... CLS>
+static const void* kernel_ptr(int cls, std::integer_sequence<int, CLS...>)
+{
+    const void* r = nullptr;
+    ((r = r ? r : kernel_ptr_one<R, CLS>(cls)), ...);
+    return r;
+}
+
+const void* short_kernel_ptr(bool fp32, int cls)
+{
+    return fp32 ? kernel_ptr<float>(cls, std::make_integer_sequence<int, kNumClasses>{})
+                : kernel_ptr<double>(cls, std::make_integer_sequence<int, kNumClasses>{});
+}
+
+}  // namespace phmm

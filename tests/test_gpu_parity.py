@@ -1,0 +1,254 @@
+"""Parity of the gfx950 kernels against the FP64 oracle, through the C ABI.
+
+Tolerances (abs difference of log10 L):
+  FP32-accepted results  <= 1e-4
+  FP64 results (plain, rerun, long/rescaled) <= 1e-10
+The FP32 acceptance rule (scaled sum >= 1e-28, i.e. log10 L >= -64.1236) is
+checked against the oracle's value outside a +-1e-3 band around the threshold.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import paper_2606_25738_amd as phmm  # noqa: E402
+import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-4
+TOL64 = 1e-10
+THRESH = -28.0 - 120 * math.log10(2.0)  # log10 L at scaled sum 1e-28
+
+
+@pytest.fixture(scope="module")
+def ctx64():
+    c = phmm.Context(precision=phmm.PHMM_FP64_PLAIN)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx32():
+    c = phmm.Context(precision=phmm.PHMM_FP32_RERUN)
+    yield c
+    c.close()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def check(batch, got, flags, idx=None, tol32=TOL32, tol64=TOL64, plain64=False):
+    """Compare against the oracle on all pairs (idx None) or a sample."""
+    if idx is None:
+        idx = np.arange(len(batch["pair_list"]))
+    want = oracle.forward_pairs(batch, idx, rescale=True)
+    g, f = got[idx], flags[idx]
+    # L = 0 exactly (e.g. T_DM = 0) is -inf on both sides
+    assert np.array_equal(np.isfinite(g), np.isfinite(want)), "finite/non-finite mismatch"
+    assert not np.isnan(g).any()
+    fin = np.isfinite(want)
+    d = np.where(fin, np.abs(np.where(fin, g, 0.0) - np.where(fin, want, 0.0)), 0.0)
+    is32 = (f & phmm.PHMM_FLAG_FP32) != 0
+    is64 = (f & phmm.PHMM_FLAG_FP64) != 0
+    assert np.all(is32 ^ is64), "every pair has exactly one precision flag"
+    if plain64:
+        assert not is32.any()
+    if is32.any():
+        assert d[is32].max() <= tol32, "FP32 max err %g" % d[is32].max()
+    if is64.any():
+        assert d[is64].max() <= tol64, "FP64 max err %g" % d[is64].max()
+    return want, d
+
+
+def test_cfg0_fp64_plain(ctx64):
+    b = synth.generate("cfg0")
+    say("cfg0 fp64 plain: 512 pairs")
+    out, fl = phmm.phmm_forward_batch(ctx64, b)
+    want, d = check(b, out, fl, plain64=True)
+    assert np.all(fl == phmm.PHMM_FLAG_FP64)
+    say("  max |dlog10| = %.3g" % d.max())
+
+
+def test_cfg0_fp32_rerun_policy(ctx32):
+    b = synth.generate("cfg0")
+    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    want, d = check(b, out, fl)
+    rerun = (fl & phmm.PHMM_FLAG_RERUN) != 0
+    # the acceptance rule follows the oracle's likelihood (outside the band)
+    assert np.all(rerun[want < THRESH - 1e-3])
+    assert not np.any(rerun[want > THRESH + 1e-3])
+    say("cfg0 fp32: rerun %d of %d, max err fp32 %.3g" % (rerun.sum(), len(out),
+                                                          d[~rerun].max() if (~rerun).any() else 0))
+
+
+def test_cfg1_sample_fp32_rerun(ctx32):
+    b = synth.generate("cfg1", 0, 60)
+    n = len(b["pair_list"])
+    say("cfg1 60 regions: %d pairs, %.3g cells" % (n, synth.batch_cells(b)))
+    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(n, size=min(n, 1500), replace=False))
+    check(b, out, fl, idx)
+
+
+def test_cfg3_sample_fp32_rerun(ctx32):
+    b = synth.generate("cfg3", 0, 40)
+    n = len(b["pair_list"])
+    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    rng = np.random.default_rng(12)
+    idx = np.sort(rng.choice(n, size=min(n, 1500), replace=False))
+    check(b, out, fl, idx)
+
+
+@pytest.mark.parametrize("cls", range(11))
+def test_every_class_fp32_and_fp64(cls):
+    """Force each column class; pairs too long for it fall back to the widest."""
+    b = synth.generate("cfg1", 100, 6)
+    n = len(b["pair_list"])
+    idx = np.arange(0, n, max(1, n // 200))
+    for prec in (phmm.PHMM_FP32_RERUN, phmm.PHMM_FP64_PLAIN):
+        with phmm.Context(precision=prec, force_class=cls) as c:
+            out, fl = phmm.phmm_forward_batch(c, b)
+        check(b, out, fl, idx, plain64=prec == phmm.PHMM_FP64_PLAIN)
+
+
+def test_packing_is_bit_exact():
+    """A pair gives the same bits alone in its wavefront or packed with others."""
+    b = synth.generate("cfg1", 7, 5)
+    for cls in (2, 6, 10):
+        with phmm.Context(force_class=cls) as c:
+            packed, f1 = phmm.phmm_forward_batch(c, b)
+        with phmm.Context(force_class=cls, one_pair_per_wave=True) as c:
+            alone, f2 = phmm.phmm_forward_batch(c, b)
+        assert np.array_equal(f1, f2)
+        assert np.array_equal(packed.view(np.uint64), alone.view(np.uint64))
+
+
+def test_deterministic(ctx32):
+    b = synth.generate("cfg1", 3, 8)
+    a, fa = phmm.phmm_forward_batch(ctx32, b)
+    c, fc = phmm.phmm_forward_batch(ctx32, b)
+    assert np.array_equal(a.view(np.uint64), c.view(np.uint64)) and np.array_equal(fa, fc)
+
+
+def make_batch(pairs):
+    """pairs: list of (read, hap, bq, iq, dq, gq) with bytes / int arrays."""
+    reads, haps, bq, iq, dq, gq, ro, ho, pl = [], [], [], [], [], [], [0], [0], []
+    for r, h, q, i, d, g in pairs:
+        reads.append(np.frombuffer(r, np.uint8))
+        haps.append(np.frombuffer(h, np.uint8))
+        for lst, v in ((bq, q), (iq, i), (dq, d), (gq, g)):
+            lst.append(np.broadcast_to(np.asarray(v, np.uint8), (len(r),)))
+        ro.append(ro[-1] + len(r))
+        ho.append(ho[-1] + len(h))
+        pl.append((len(ro) - 2, len(ho) - 2))
+    cat = lambda x: np.ascontiguousarray(np.concatenate(x).astype(np.uint8))
+    return dict(reads=cat(reads), base_quals=cat(bq), ins_quals=cat(iq), del_quals=cat(dq),
+                gcp=cat(gq), read_offsets=np.array(ro, np.uint64),
+                haplotypes=cat(haps), hap_offsets=np.array(ho, np.uint64),
+                pair_list=np.array(pl, np.uint32))
+
+
+def rnd(rng, n, alpha=b"ACGT"):
+    a = np.frombuffer(alpha, np.uint8)
+    return bytes(a[rng.integers(0, len(a), n)])
+
+
+def test_edge_cases(ctx32, ctx64):
+    rng = np.random.default_rng(5)
+    src = rnd(rng, 3000)
+    pairs = [
+        (b"A", b"A", 30, 45, 45, 10),
+        (b"A", b"C", 30, 45, 45, 10),
+        (b"ACGT", b"A", 20, 45, 45, 10),
+        (b"A", rnd(rng, 97), 20, 45, 45, 10),
+        (b"N" * 30, rnd(rng, 50), 20, 45, 45, 10),
+        (rnd(rng, 30), b"N" * 40, 20, 45, 45, 10),
+        (rnd(rng, 40, b"ACGTN"), rnd(rng, 60, b"ACGTN"), 25, 40, 40, 10),
+        (src[100:250], src[90:90 + 64 * 4], 30, 45, 45, 10),           # exactly 64 lanes x 4
+        (src[100:250], src[90:90 + 64 * 24], 30, 45, 45, 10),          # widest short pair
+        (src[100:250], src[90:90 + 64 * 24 + 1], 30, 45, 45, 10),      # first long pair
+        (src[0:150], src[0:150], 0, 0, 0, 0),                           # Phred 0 everywhere
+        (src[0:150], src[0:150], 255, 255, 255, 255),                   # Phred 255 everywhere
+        (src[5:120], src[0:300], np.arange(115) % 60, 30, 30, np.arange(115) % 40 + 1),
+    ]
+    b = make_batch(pairs)
+    for c, plain in ((ctx64, True), (ctx32, False)):
+        out, fl = phmm.phmm_forward_batch(c, b)
+        check(b, out, fl, plain64=plain)
+
+
+def test_unsorted_pairs_and_duplicates(ctx32):
+    b = synth.generate("cfg1", 11, 3)
+    pl = b["pair_list"]
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(len(pl))
+    b2 = dict(b)
+    b2["pair_list"] = np.ascontiguousarray(np.concatenate([pl[perm], pl[perm[:50]]]))
+    out, fl = phmm.phmm_forward_batch(ctx32, b2)
+    check(b2, out, fl)
+    # duplicates of a pair give identical bits
+    n = len(pl)
+    assert np.array_equal(out[:50].view(np.uint64), out[n:n + 50].view(np.uint64))
+
+
+def test_long_pairs_multi_tile(ctx32):
+    rng = np.random.default_rng(9)
+    pairs = []
+    for k in (1537, 2048, 3000, 5000):
+        hap = rnd(rng, k)
+        read = bytearray(hap[10:10 + 300])
+        for j in rng.integers(0, 300, 6):
+            read[j] = ord("ACGT"[int(rng.integers(0, 4))])
+        pairs.append((bytes(read), hap, rng.integers(10, 40, 300), 30, 30, 10))
+    b = make_batch(pairs)
+    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    assert np.all(fl & phmm.PHMM_FLAG_LONG)
+    check(b, out, fl)
+
+
+def test_fp64_underflow_goes_to_rescaled_kernel(ctx64):
+    rng = np.random.default_rng(10)
+    pairs = [(rnd(rng, 600), rnd(rng, 700), 40, 45, 45, 10)]  # log10 L ~ -2700
+    b = make_batch(pairs)
+    out, fl = phmm.phmm_forward_batch(ctx64, b)
+    assert fl[0] & phmm.PHMM_FLAG_RESCALED
+    want, d = check(b, out, fl, plain64=True)
+    assert want[0] < -1000
+
+
+def test_cfg2_long_read_10k(ctx32):
+    b = synth.generate("cfg2", 0, 1)  # one 10 kbp read x 11 kbp haplotype
+    say("cfg2 region 0: read %d, hap %d" % (int(np.diff(b["read_offsets"])[0]),
+                                            int(np.diff(b["hap_offsets"])[0])))
+    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    want, d = check(b, out, fl)
+    say("  log10 L = %.6f (oracle %.6f)" % (out[0], want[0]))
+
+
+def test_async_matches_sync(ctx32):
+    import torch
+    b = synth.generate("cfg1", 20, 10)
+    sync_out, sync_fl = phmm.phmm_forward_batch(ctx32, b)
+    db = phmm.DeviceBatch(b)
+    n = db.n_pairs
+    ws_bytes = phmm.phmm_workspace_bytes(ctx32, n, db.max_read_len, db.max_hap_len)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda:0")
+    out = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    fl = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    s = torch.cuda.Stream()
+    phmm.phmm_forward_batch_async(ctx32, db, out, fl, ws, s)
+    s.synchronize()
+    phmm.phmm_device_status(ctx32, ws)
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), sync_out.view(np.uint64))
+    assert np.array_equal(fl.cpu().numpy(), sync_fl)
+    counts = phmm.phmm_last_counts(ctx32, ws)
+    assert counts["packs_fp32"] > 0
