@@ -127,10 +127,21 @@ int oracle_forward_probs(const double* pri, const uint8_t* read, int l,
             if (s > 0.0) {
                 int e;
                 frexp(s, &e);
-                for (size_t j = 0; j < n; ++j) {
-                    Mc[j] = ldexp(Mc[j], -e);
-                    Ic[j] = ldexp(Ic[j], -e);
-                    Dc[j] = ldexp(Dc[j], -e);
+                if (e > -1000 && e < 1000) {
+                    /* 2^-e is a normal double: x * 2^-e is the correctly
+                     * rounded value of the same exact product as ldexp. */
+                    const double f = ldexp(1.0, -e);
+                    for (size_t j = 0; j < n; ++j) {
+                        Mc[j] = Mc[j] * f;
+                        Ic[j] = Ic[j] * f;
+                        Dc[j] = Dc[j] * f;
+                    }
+                } else {
+                    for (size_t j = 0; j < n; ++j) {
+                        Mc[j] = ldexp(Mc[j], -e);
+                        Ic[j] = ldexp(Ic[j], -e);
+                        Dc[j] = ldexp(Dc[j], -e);
+                    }
                 }
                 ex += e;
             }
