@@ -24,13 +24,15 @@
 // long reads): every kRescaleRows rows a tile multiplies its state by 2^-e,
 // e the exponent of its largest value, and adds e to an integer exponent E.
 // Values handed between tiles carry the producer's exponent and are brought
-// into the consumer's scale with ldexp.  The start row is D(0,j) = 1/k and the
+// into the consumer's scale with ldexp; when a record lies more than
+// kRebaseBits above the consumer's scale the consumer first rebases to it.  The start row is D(0,j) = 1/k and the
 // result is log10(S) + E log10(2).
 #include "phmm_dev.h"
 
 namespace phmm {
 
 constexpr int kRescaleRows = 8;
+constexpr long long kRebaseBits = 256;  // rebase when a neighbour's record is this far above
 constexpr double kExpBias = 1099511627776.0;  // 2^40: exponents stored as E + 2^40
 
 __host__ __device__ uint32_t long_slots(int grid) { return 2u * (uint32_t)(grid > 0 ? grid : 1); }
@@ -380,10 +382,30 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
                     }
                     const int q = i - rb;
                     const long long Ep = (long long)(magnitude(rd_lane(bE, q)) - kExpBias);
+                    const double rM = magnitude(rd_lane(bM, q)), rI = magnitude(rd_lane(bI, q));
+                    const double rP = magnitude(rd_lane(bP, q));
+                    // Within a tile values fall by T_DD per column away from the
+                    // alignment band, so a neighbour's boundary can sit far above
+                    // this tile's scale (this tile's own values are then
+                    // negligible).  Rebase before converting so the record stays
+                    // representable.
+                    const double mrec = fmax(rM, fmax(rI, rP));
+                    if (mrec > 0.0) {
+                        int er;
+                        frexp(mrec, &er);
+                        if (Ep + er - E > kRebaseBits) {
+                            const long long enew = Ep + er;
+                            const double f = ldexp(1.0, (int)max(E - enew, -2000LL));
+#pragma unroll
+                            for (int n = 0; n < N; ++n) { Mp[n] *= f; Ip[n] *= f; }
+                            Vp *= f;
+                            E = enew;
+                        }
+                    }
                     const int sh = (int)max(min(Ep - E, 2000LL), -2000LL);
-                    nbM = ldexp(magnitude(rd_lane(bM, q)), sh);
-                    nbI = ldexp(magnitude(rd_lane(bI, q)), sh);
-                    nbP = ldexp(magnitude(rd_lane(bP, q)), sh);
+                    nbM = ldexp(rM, sh);
+                    nbI = ldexp(rI, sh);
+                    nbP = ldexp(rP, sh);
                 }
                 Mleft = dpp<kWaveShr1>(Mp[N - 1]);
                 Ileft = dpp<kWaveShr1>(Ip[N - 1]);

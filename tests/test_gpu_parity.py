@@ -223,13 +223,15 @@ def test_long_pairs_multi_tile(ctx32):
 
 
 def test_fp64_underflow_goes_to_rescaled_kernel(ctx64):
+    """A short pair whose FP64 scaled sum underflows (log10 L < -597) is
+    recomputed by the rescaling kernel."""
     rng = np.random.default_rng(10)
-    pairs = [(rnd(rng, 600), rnd(rng, 700), 40, 45, 45, 10)]  # log10 L ~ -2700
+    pairs = [(rnd(rng, 1000), rnd(rng, 1200), 40, 45, 45, 10)]
     b = make_batch(pairs)
     out, fl = phmm.phmm_forward_batch(ctx64, b)
-    assert fl[0] & phmm.PHMM_FLAG_RESCALED
     want, d = check(b, out, fl, plain64=True)
-    assert want[0] < -1000
+    assert want[0] < -700
+    assert fl[0] & phmm.PHMM_FLAG_RESCALED
 
 
 def test_cfg2_long_read_10k(ctx32):
@@ -239,6 +241,13 @@ def test_cfg2_long_read_10k(ctx32):
     out, fl = phmm.phmm_forward_batch(ctx32, b)
     want, d = check(b, out, fl)
     say("  log10 L = %.6f (oracle %.6f)" % (out[0], want[0]))
+
+
+def test_cfg2_long_read_32k(ctx32):
+    b = synth.generate("cfg2", 32, 1)  # one 32 kbp read x 35.2 kbp haplotype (35 tiles)
+    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    want, d = check(b, out, fl)
+    say("cfg2 region 32: log10 L = %.6f (oracle %.6f)" % (out[0], want[0]))
 
 
 def test_async_matches_sync(ctx32):
