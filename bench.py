@@ -144,6 +144,8 @@ def main():
     out = torch.empty(n_pairs, dtype=torch.float64, device="cuda:0")
     fl = torch.empty(n_pairs, dtype=torch.uint8, device="cuda:0")
 
+    peak32, peak64 = phmm.phmm_vector_peak(0)
+    log("measured vector FMA peak: FP32 %.1f TFLOP/s, FP64 %.1f TFLOP/s" % (peak32, peak64))
     ctx = phmm.Context(timing=True)
     ws = torch.empty(phmm.phmm_workspace_bytes(ctx, n_pairs, db.max_read_len, db.max_hap_len),
                      dtype=torch.uint8, device="cuda:0")
@@ -161,7 +163,9 @@ def main():
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                 frac=round(achieved / FP32_PEAK_TFLOPS, 4), traffic=None,
                 kernel="FP32 short-pair kernels (11 column-class launches per step)",
-                kernel_ms=round(ph["short_ms"], 3))
+                kernel_ms=round(ph["short_ms"], 3),
+                measured_peak_fp32=round(peak32, 2), measured_peak_fp64=round(peak64, 2),
+                frac_of_measured=round(achieved / peak32, 4))
 
     fp64 = None
     if args.fp64_steps > 0:

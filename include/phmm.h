@@ -233,6 +233,13 @@ typedef struct phmm_timing {
 } phmm_timing;
 int phmm_last_timing(phmm_ctx* ctx, phmm_timing* out);
 
+/* Calibration: measures the device's achievable vector FMA rates (FP32
+ * scalar FMA and FP64 FMA, TFLOP/s with an FMA counted as two flops) with
+ * independent FMA chains in every lane.  Used to state the ALU roofline the
+ * kernels are measured against.  Errors: PHMM_EINVAL (NULL output),
+ * PHMM_EDEVICE. */
+int phmm_vector_peak(int device, double* fp32_tflops, double* fp64_tflops);
+
 #ifdef __cplusplus
 }
 #endif

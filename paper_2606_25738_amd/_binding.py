@@ -104,6 +104,8 @@ def lib():
             L.phmm_device_status.argtypes = [vp, vp]
             L.phmm_last_counts.argtypes = [vp, vp, ctypes.POINTER(_Counts)]
             L.phmm_last_timing.argtypes = [vp, ctypes.POINTER(_Timing)]
+            L.phmm_vector_peak.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double)]
             _lib = L
     return _lib
 
@@ -291,6 +293,13 @@ def phmm_last_counts(ctx: Context, workspace) -> dict:
     c = _Counts()
     _check(lib().phmm_last_counts(ctx.handle, workspace.data_ptr(), ctypes.byref(c)))
     return {n: getattr(c, n) for n, _ in _Counts._fields_}
+
+
+def phmm_vector_peak(device: int = 0) -> tuple[float, float]:
+    """Measured (FP32, FP64) vector FMA TFLOP/s of the device."""
+    a, b = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib().phmm_vector_peak(device, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def phmm_last_timing(ctx: Context) -> dict:

@@ -19,8 +19,8 @@ void launch_short(bool fp32, int cls, int grid, hipStream_t s, const Batch& b, c
                   const Work& w, const Policy& p);
 const void* short_kernel_ptr(bool fp32, int cls);
 __global__ void reset_kernel(Counters* c);
-__global__ void pack_plan_kernel(Batch b, Work w, Policy pol);
-__global__ void pack_layout_kernel(Counters* c);
+__global__ void pack_count_kernel(Batch b, Work w, Policy pol);
+__global__ void pack_scan_kernel(Work w, uint32_t nblocks);
 __global__ void pack_emit_kernel(Batch b, Work w, Policy pol);
 void launch_long(hipStream_t s, int grid, const Batch& b, const Tables& t, const Work& w,
                  const Policy& p);
@@ -213,8 +213,11 @@ extern "C" int phmm_create(phmm_ctx** out, int device, const phmm_options* opt)
 
 // ---------------------------------------------------------------- workspace
 struct Layout {
-    size_t ctr, chunk_info, packs, items, long_list, long_pref, ring, slot, part, total;
+    size_t ctr, chunk_info, blk_cnt, blk_lc, packs, items, long_list, long_pref, ring, slot, part,
+        total;
 };
+
+static uint64_t pack_blocks(uint64_t n_pairs) { return (n_pairs + kPackBlock - 1) / kPackBlock; }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -226,6 +229,8 @@ static Layout layout_for(const phmm_ctx* c, uint64_t n_pairs)
     const uint32_t slots = long_slots(c->grid_long);
     L.ctr = o; o = align256(o + sizeof(Counters));
     L.chunk_info = o; o = align256(o + n * 4);
+    L.blk_cnt = o; o = align256(o + pack_blocks(n) * 2 * kNumClasses * 4);
+    L.blk_lc = o; o = align256(o + pack_blocks(n) * 8);
     L.packs = o; o = align256(o + n * sizeof(Pack));
     L.items = o; o = align256(o + n * sizeof(Item));
     L.long_list = o; o = align256(o + n * 4);
@@ -253,6 +258,8 @@ static Work work_for(phmm_ctx* c, void* ws, uint64_t n_pairs)
     Work w;
     w.ctr = reinterpret_cast<Counters*>(base + L.ctr);
     w.chunk_info = reinterpret_cast<uint32_t*>(base + L.chunk_info);
+    w.blk_cnt = reinterpret_cast<uint32_t*>(base + L.blk_cnt);
+    w.blk_lanecols = reinterpret_cast<unsigned long long*>(base + L.blk_lc);
     w.packs = reinterpret_cast<Pack*>(base + L.packs);
     w.items = reinterpret_cast<Item*>(base + L.items);
     w.long_list = reinterpret_cast<uint32_t*>(base + L.long_list);
@@ -278,10 +285,10 @@ static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s)
     if (timed) HIP_TRY(hipEventRecord(c->ev[0], s));
     hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, s, w.ctr);
     if (b.n_pairs > 0) {
-        const unsigned blocks = (unsigned)((b.n_pairs + 255) / 256);
-        hipLaunchKernelGGL(pack_plan_kernel, dim3(blocks), dim3(256), 0, s, b, w, pol);
-        hipLaunchKernelGGL(pack_layout_kernel, dim3(1), dim3(64), 0, s, w.ctr);
-        hipLaunchKernelGGL(pack_emit_kernel, dim3(blocks), dim3(256), 0, s, b, w, pol);
+        const unsigned blocks = (unsigned)pack_blocks(b.n_pairs);
+        hipLaunchKernelGGL(pack_count_kernel, dim3(blocks), dim3(kPackBlock), 0, s, b, w, pol);
+        hipLaunchKernelGGL(pack_scan_kernel, dim3(1), dim3(1024), 0, s, w, (uint32_t)blocks);
+        hipLaunchKernelGGL(pack_emit_kernel, dim3(blocks), dim3(kPackBlock), 0, s, b, w, pol);
     }
     if (timed) HIP_TRY(hipEventRecord(c->ev[1], s));
     if (b.n_pairs > 0) {

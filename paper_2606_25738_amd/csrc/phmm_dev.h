@@ -105,30 +105,37 @@ __device__ __forceinline__ R seg_scan(R x, const ScanMul<R>& m)
     return x;
 }
 
-// Haplotype columns are held as floats whose IEEE class names the base, so
-// one class test against a per-row mask decides match / mismatch:
-//   A = +1.0 (+normal)  C = -1.0 (-normal)  G = +0.0  T = -0.0
-//   N = +inf (in every mask: matches any read base)  padding = -inf (in none)
-// Class-mask bits (v_cmp_class): 3 -normal, 5 -zero, 6 +zero, 8 +normal, 9 +inf.
-__device__ __forceinline__ float hap_class_value(uint8_t b)
+// Emission select without compares.  Each haplotype column is an 8-bit
+// code with bit b set when a read base of index b matches it (A=0, C=1,
+// G=2, T=3) and bit 4 always set; 'N' sets bits 0-3, padding sets only bit 4
+// (padding columns never influence real ones).  Four columns share a 32-bit
+// register.  A row whose read base has index b (4 for 'N', which matches
+// everything) extracts bit 8*n+b as a signed 1-bit field: -1 on a match, 0
+// otherwise, and that mask picks pm or px bit-wise (v_bfe_i32 + v_bfi_b32).
+__device__ __forceinline__ uint32_t hap_code(uint8_t b)
 {
-    uint32_t u = b == 'A' ? 0x3f800000u : b == 'C' ? 0xbf800000u : b == 'G' ? 0x00000000u
-               : b == 'T' ? 0x80000000u : 0x7f800000u;  // N (and any other byte)
-    return __builtin_bit_cast(float, u);
+    return b == 'A' ? 0x11u : b == 'C' ? 0x12u : b == 'G' ? 0x14u : b == 'T' ? 0x18u
+         : 0x1fu;  // N (and any other byte)
 }
-__device__ __forceinline__ float hap_pad_value() { return __builtin_bit_cast(float, 0xff800000u); }
+constexpr uint32_t kPadCode = 0x10u;
 
-// Class mask selecting the haplotype columns that match read base b.
-__device__ __forceinline__ int read_class_mask(uint8_t b)
+__device__ __forceinline__ int read_base_index(uint8_t b)
 {
-    return b == 'A' ? ((1 << 8) | (1 << 9)) : b == 'C' ? ((1 << 3) | (1 << 9))
-         : b == 'G' ? ((1 << 6) | (1 << 9)) : b == 'T' ? ((1 << 5) | (1 << 9))
-         : 0x3ff;  // N: every column matches
+    return b == 'A' ? 0 : b == 'C' ? 1 : b == 'G' ? 2 : b == 'T' ? 3 : 4;
 }
 
-__device__ __forceinline__ bool col_match(float hv, int mask)
+// pm if column n (code word w, bit offset off = 8*(n%4) + base index) matches
+__device__ __forceinline__ float emit_sel(uint32_t w, int off, float pm, float px)
 {
-    return __builtin_amdgcn_class(hv, mask);
+    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)w, off, 1);
+    return __builtin_bit_cast(float, (m & __builtin_bit_cast(uint32_t, pm)) |
+                                         (~m & __builtin_bit_cast(uint32_t, px)));
+}
+__device__ __forceinline__ double emit_sel(uint32_t w, int off, double pm, double px)
+{
+    const uint64_t m = (uint64_t)(int64_t)__builtin_amdgcn_sbfe((int)w, off, 1);
+    return __builtin_bit_cast(double, (m & __builtin_bit_cast(uint64_t, pm)) |
+                                          (~m & __builtin_bit_cast(uint64_t, px)));
 }
 
 __device__ __forceinline__ uint32_t wave_broadcast0(uint32_t x)

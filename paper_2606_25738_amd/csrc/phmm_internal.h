@@ -24,6 +24,7 @@ constexpr int kWave = 64;
 constexpr uint32_t kShortMaxCols = kWave * kMaxN;  // longer haplotypes use the long kernel
 constexpr int kMaxPairsPerPack = 32;                // pair mask is 32 bits
 constexpr int kChunk = 256;                         // pairs walked by one packer thread
+constexpr int kPackBlock = 256;                     // packer threads per workgroup
 
 // Power table: for class c and gap-continuation Phred byte q, entry m
 // (0..64) holds g^(N*m) with g = 10^(-q/10); entry 65 holds g^(N-1).
@@ -39,7 +40,7 @@ struct Pack {
     uint32_t npairs;      // consecutive pairs, all of the same read
 };
 
-struct Item {             // FP64 work item: a pack and the subset of its pairs
+struct Item {             // FP64 rerun item: an FP32 pack and the subset of its pairs
     uint32_t pack;        // global pack index
     uint32_t mask;        // bit s: pair pair_start + s is computed
 };
@@ -50,7 +51,7 @@ struct Counters {
     uint32_t pack_base[2][kNumClasses];
     uint32_t pack_fill[2][kNumClasses];
     uint32_t item_base[kNumClasses];
-    uint32_t item_cnt[kNumClasses];      // FP64 items: plain packs, then reruns
+    uint32_t item_cnt[kNumClasses];      // rerun items queued by the FP32 kernels
     uint32_t cursor32[kNumClasses];
     uint32_t cursor64[kNumClasses];
     uint32_t n_long;
@@ -88,6 +89,8 @@ struct Tables {
 struct Work {
     Counters* ctr;
     uint32_t* chunk_info;  // per pair (chunk starts only)
+    uint32_t* blk_cnt;     // per packer block and segment: pack count, then offset
+    unsigned long long* blk_lanecols;
     Pack* packs;           // pack array, segments per (precision, class)
     Item* items;           // FP64 items, segments per class
     uint32_t* long_list;   // long pair indices

@@ -145,40 +145,42 @@ struct LRec {
     double dp, px, tmm, tim, cd, tmi, tii, pm;
 };
 
-__device__ __forceinline__ void lrow_first(double (&Mp)[kLongN], double (&Ip)[kLongN],
-                                           const float (&hv)[kLongN], int cmask, const LRec& c,
-                                           double minit, double g, double& Vp)
+constexpr int kLongWords = kLongN / 4;
+
+__device__ __forceinline__ void lrow_first(double (&Mo)[kLongN], double (&Io)[kLongN],
+                                           const uint32_t (&hc)[kLongWords], int bidx,
+                                           const LRec& c, double minit, double g, double& Vp)
 {
     double V = 0.0;
     const double base = c.tim * minit;
 #pragma unroll
     for (int n = 0; n < kLongN; ++n) {
-        const double p = col_match(hv[n], cmask) ? c.pm : c.px;
+        const double p = emit_sel(hc[n / 4], 8 * (n % 4) + bidx, c.pm, c.px);
         const double m = p * base;
-        Mp[n] = m;
-        Ip[n] = 0.0;
+        Mo[n] = m;
+        Io[n] = 0.0;
         if (n < kLongN - 1) V = __builtin_fma(g, V, m);
     }
     Vp = V;
 }
 
-__device__ __forceinline__ void lrow_step(double (&Mp)[kLongN], double (&Ip)[kLongN],
-                                          const float (&hv)[kLongN], int cmask, const LRec& c,
-                                          double Mleft, double Ileft, double C, double gprev,
-                                          double gcur, double& Vp)
+__device__ __forceinline__ void lrow_step(const double (&Mi)[kLongN], const double (&Ii)[kLongN],
+                                          double (&Mo)[kLongN], double (&Io)[kLongN],
+                                          const uint32_t (&hc)[kLongWords], int bidx,
+                                          const LRec& c, double Mleft, double Ileft, double C,
+                                          double gprev, double gcur, double& Vp)
 {
-    double T = C, mprev = Mleft, iprev = Ileft, V = 0.0;
+    double T = C, V = 0.0;
 #pragma unroll
     for (int n = 0; n < kLongN; ++n) {
-        const double p = col_match(hv[n], cmask) ? c.pm : c.px;
+        const double mprev = n == 0 ? Mleft : Mi[n - 1];
+        const double iprev = n == 0 ? Ileft : Ii[n - 1];
+        const double p = emit_sel(hc[n / 4], 8 * (n % 4) + bidx, c.pm, c.px);
         const double x = __builtin_fma(c.cd, T, __builtin_fma(c.tim, iprev, c.tmm * mprev));
         const double m = p * x;
-        const double in = __builtin_fma(c.tii, Ip[n], c.tmi * Mp[n]);
+        Mo[n] = m;
+        Io[n] = __builtin_fma(c.tii, Ii[n], c.tmi * Mi[n]);
         T = __builtin_fma(gprev, T, mprev);
-        mprev = Mp[n];
-        iprev = Ip[n];
-        Mp[n] = m;
-        Ip[n] = in;
         if (n < kLongN - 1) V = __builtin_fma(gcur, V, m);
     }
     Vp = V;
@@ -281,13 +283,16 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
         }
         if (__ballot(dead) != 0ull) break;
 
-        // ---- columns of this lane, class-coded (see hap_class_value)
+        // ---- columns of this lane as 8-bit match codes, four per register
         const uint32_t c0 = tile * (uint32_t)kLongTile + (uint32_t)lane * N;
-        float hv[N];
+        uint32_t hc[kLongWords];
+#pragma unroll
+        for (int q = 0; q < kLongWords; ++q) hc[q] = 0u;
 #pragma unroll
         for (int n = 0; n < N; ++n) {
             const uint32_t j = c0 + (uint32_t)n;
-            hv[n] = j < k ? hap_class_value(b.haps[hoff + j]) : hap_pad_value();
+            const uint32_t code = j < k ? hap_code(b.haps[hoff + j]) : kPadCode;
+            hc[n / 4] |= code << (8 * (n % 4));
         }
         const double minit = 1.0 / (double)k;
         const int g0 = b.gq[roff];
@@ -296,9 +301,10 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
         double gcur = t.p64[g0], gprev = gcur, gN1 = pw0[65], gN = pw0[1];
         const ScanMul<double> ones = make_sum_mul<double>(lane, 0);
 
-        double Mp[N], Ip[N];
+        // rows alternate between the (Ma, Ia) and (Mb, Ib) register sets
+        double Ma[N], Ia[N], Mb[N], Ib[N];
 #pragma unroll
-        for (int n = 0; n < N; ++n) { Mp[n] = 0.0; Ip[n] = 0.0; }
+        for (int n = 0; n < N; ++n) { Ma[n] = 0.0; Ia[n] = 0.0; Mb[n] = 0.0; Ib[n] = 0.0; }
         double Mleft = 0.0, Ileft = 0.0, C = 0.0;
         long long E = 0;
         // producer records buffered one per lane: rows rb .. rb+nvalid-1
@@ -331,12 +337,14 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
                     rr.tii = g;
                     rr.pm = pm;
                     rec[lane] = rr;
-                    rinfo[lane] = read_class_mask(b.reads[a]) | (gc << 16);
+                    rinfo[lane] = read_base_index(b.reads[a]) | (gc << 16);
                 }
             }
             __syncthreads();
             const int nrows = l - i0 < kWave ? l - i0 : kWave;
-            for (int tt = 0; tt < nrows; ++tt) {
+            // one row: Mp/Ip name the register set that receives row i
+            auto do_row = [&](int tt, const double(&Mi)[N], const double(&Ii)[N], double(&Mp)[N],
+                              double(&Ip)[N]) -> bool {
                 const int i = i0 + tt;
                 const LRec c = rec[tt];
                 const int info = __builtin_amdgcn_readfirstlane(rinfo[tt]);
@@ -350,9 +358,9 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
                     gN = pwi[1];
                 }
                 double Vp;
-                const int cmask = info & 0xffff;
-                if (i == 0) lrow_first(Mp, Ip, hv, cmask, c, minit, gcur, Vp);
-                else lrow_step(Mp, Ip, hv, cmask, c, Mleft, Ileft, C, gprev, gcur, Vp);
+                const int bidx = info & 0xff;
+                if (i == 0) lrow_first(Mp, Ip, hc, bidx, c, minit, gcur, Vp);
+                else lrow_step(Mi, Ii, Mp, Ip, hc, bidx, c, Mleft, Ileft, C, gprev, gcur, Vp);
                 double nbM = 0.0, nbI = 0.0, nbP = 0.0;
                 if (has_prod) {
                     if (i >= rb + nvalid) {  // refill the record buffer
@@ -378,7 +386,7 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
                             if ((spins & 63u) == 0u && aborted(w)) { dead = true; break; }
                             __builtin_amdgcn_s_sleep(1);
                         }
-                        if (dead) break;
+                        if (dead) return false;
                     }
                     const int q = i - rb;
                     const long long Ep = (long long)(magnitude(rd_lane(bE, q)) - kExpBias);
@@ -425,7 +433,7 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
                             if ((spins & 63u) == 0u && aborted(w)) { dead = true; break; }
                             __builtin_amdgcn_s_sleep(2);
                         }
-                        if (dead) break;
+                        if (dead) return false;
                     }
                     if (lane == 63) {
                         const uint32_t par = ((uint32_t)i / kRing) & 1u;
@@ -458,6 +466,18 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
                         E += e;
                     }
                 }
+                return true;
+            };
+            int tt = 0;
+            for (; tt + 1 < nrows; tt += 2) {
+                if (!do_row(tt, Ma, Ia, Mb, Ib)) break;
+                if (!do_row(tt + 1, Mb, Ib, Ma, Ia)) break;
+            }
+            if (!dead && tt < nrows) {
+                if (do_row(tt, Ma, Ia, Mb, Ib)) {
+#pragma unroll
+                    for (int n = 0; n < N; ++n) { Ma[n] = Mb[n]; Ia[n] = Ib[n]; }
+                }
             }
         }
         if (__ballot(dead) != 0ull) break;
@@ -466,7 +486,7 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
         double sp = 0.0;
 #pragma unroll
         for (int n = 0; n < N; ++n)
-            if (c0 + (uint32_t)n < k) sp += Mp[n] + Ip[n];
+            if (c0 + (uint32_t)n < k) sp += Ma[n] + Ia[n];
         sp = seg_scan(sp, ones);
         double am = rd_lane(sp, 63);
         long long aE = E;

@@ -62,42 +62,45 @@ __device__ __forceinline__ const double* pow_table<double>(const Tables& t, int 
     return t.pw64 + ((size_t)cls * 256 + gcp) * kPowStride;
 }
 
+constexpr int words_for(int n) { return (n + 3) / 4; }
+
 // Row 1: M(1,j) = P(r_1|h_j) T_DM_1 C0/k, I(1,j) = 0.
 template <typename R, int N>
-__device__ __forceinline__ void row_first(R (&Mp)[N], R (&Ip)[N], const float (&hv)[N], int cmask,
-                                          const RowRec<R>& c, R minit, R g, R& Vp)
+__device__ __forceinline__ void row_first(R (&Mo)[N], R (&Io)[N], const uint32_t (&hc)[words_for(N)],
+                                          int bidx, const RowRec<R>& c, R minit, R g, R& Vp)
 {
     R V = (R)0;
     const R base = c.tim * minit;  // T_DM_1 = T_IM_1
 #pragma unroll
     for (int n = 0; n < N; ++n) {
-        const R p = col_match(hv[n], cmask) ? c.pm : c.px;
+        const R p = emit_sel(hc[n / 4], 8 * (n % 4) + bidx, c.pm, c.px);
         const R m = p * base;
-        Mp[n] = m;
-        Ip[n] = (R)0;
+        Mo[n] = m;
+        Io[n] = (R)0;
         if (n < N - 1) V = fmaR(g, V, m);
     }
     Vp = V;
 }
 
-// Rows 2..l of the row-level recurrence (see the file comment).
+// Rows 2..l of the row-level recurrence (see the file comment); reads row
+// i-1 from (Mi, Ii) and writes row i to (Mo, Io).
 template <typename R, int N>
-__device__ __forceinline__ void row_step(R (&Mp)[N], R (&Ip)[N], const float (&hv)[N], int cmask,
+__device__ __forceinline__ void row_step(const R (&Mi)[N], const R (&Ii)[N], R (&Mo)[N], R (&Io)[N],
+                                         const uint32_t (&hc)[words_for(N)], int bidx,
                                          const RowRec<R>& c, R Mleft, R Ileft, R C, R gprev,
                                          R gcur, R& Vp)
 {
-    R T = C, mprev = Mleft, iprev = Ileft, V = (R)0;
+    R T = C, V = (R)0;
 #pragma unroll
     for (int n = 0; n < N; ++n) {
-        const R p = col_match(hv[n], cmask) ? c.pm : c.px;
+        const R mprev = n == 0 ? Mleft : Mi[n - 1];
+        const R iprev = n == 0 ? Ileft : Ii[n - 1];
+        const R p = emit_sel(hc[n / 4], 8 * (n % 4) + bidx, c.pm, c.px);
         const R x = fmaR(c.cd, T, fmaR(c.tim, iprev, c.tmm * mprev));
         const R m = p * x;
-        const R in = fmaR(c.tii, Ip[n], c.tmi * Mp[n]);
+        Mo[n] = m;
+        Io[n] = fmaR(c.tii, Ii[n], c.tmi * Mi[n]);
         T = fmaR(gprev, T, mprev);
-        mprev = Mp[n];
-        iprev = Ip[n];
-        Mp[n] = m;
-        Ip[n] = in;
         if (n < N - 1) V = fmaR(gcur, V, m);
     }
     Vp = V;
@@ -119,8 +122,9 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
     const int lane = (int)threadIdx.x;
     Counters* ctr = w.ctr;
     uint32_t* cursor = kFP32 ? &ctr->cursor32[CLS] : &ctr->cursor64[CLS];
-    const uint32_t count = kFP32 ? ctr->pack_cnt[0][CLS] : ctr->item_cnt[CLS];
+    // FP64: the class's plain FP64 packs first, then the rerun items
     const uint32_t n_plain = ctr->pack_cnt[1][CLS];
+    const uint32_t count = kFP32 ? ctr->pack_cnt[0][CLS] : n_plain + ctr->item_cnt[CLS];
 
     for (;;) {
         uint32_t it = 0;
@@ -133,8 +137,12 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
             pack_gi = ctr->pack_base[0][CLS] + it;
             const uint32_t np = w.packs[pack_gi].npairs;
             mask = np == 32 ? 0xffffffffu : ((1u << np) - 1u);
+        } else if (it < n_plain) {
+            pack_gi = ctr->pack_base[1][CLS] + it;
+            const uint32_t np = w.packs[pack_gi].npairs;
+            mask = np == 32 ? 0xffffffffu : ((1u << np) - 1u);
         } else {
-            const Item itm = w.items[ctr->item_base[CLS] + it];
+            const Item itm = w.items[ctr->item_base[CLS] + (it - n_plain)];
             pack_gi = itm.pack;
             mask = itm.mask;
         }
@@ -182,12 +190,15 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
         const int c0 = N * (lane - segstart);
         const bool segend = real && (lane == segstart + seglanes - 1);
 
-        // ---- haplotype columns as class-coded floats (see hap_class_value)
-        float hv[N];
+        // ---- haplotype columns as 8-bit match codes, four per register
+        uint32_t hc[words_for(N)];
+#pragma unroll
+        for (int q = 0; q < words_for(N); ++q) hc[q] = 0u;
 #pragma unroll
         for (int n = 0; n < N; ++n) {
             const uint32_t j = (uint32_t)(c0 + n);
-            hv[n] = (real && j < k) ? hap_class_value(b.haps[hoff + j]) : hap_pad_value();
+            const uint32_t code = (real && j < k) ? hap_code(b.haps[hoff + j]) : kPadCode;
+            hc[n / 4] |= code << (8 * (n % 4));
         }
 
         // ---- read and its gap-continuation profile
@@ -207,10 +218,38 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
         ScanMul<R> mul = make_scan_mul<R>(pw, lane, segstart);
         R gcur = (R)t.p64[g0], gprev = gcur, gN1 = pw[65];
 
-        R Mp[N], Ip[N];
+        R Ma[N], Ia[N], Mb[N], Ib[N];
 #pragma unroll
-        for (int n = 0; n < N; ++n) { Mp[n] = (R)0; Ip[n] = (R)0; }
+        for (int n = 0; n < N; ++n) { Ma[n] = (R)0; Ia[n] = (R)0; }
         R Mleft = (R)0, Ileft = (R)0, C = (R)0;
+
+        // one row of the recurrence plus the carries for the next row; rows
+        // alternate between the (Ma, Ia) and (Mb, Ib) register sets
+        auto do_row = [&](int tt, bool first, const R(&Mi)[N], const R(&Ii)[N], R(&Mo)[N],
+                          R(&Io)[N]) {
+            const RowRec<R> c = rec[tt];
+            const int info = __builtin_amdgcn_readfirstlane(rinfo[tt]);
+            if (varying) {
+                const int gc = info >> 16;
+                gprev = gcur;
+                gcur = (R)t.p64[gc];
+                const R* pwi = pow_table<R>(t, CLS, gc);
+                mul = make_scan_mul<R>(pwi, lane, segstart);
+                gN1 = pwi[65];
+            }
+            const int bidx = info & 0xff;
+            R Vp;
+            if (first)
+                row_first<R, N>(Mo, Io, hc, bidx, c, minit, gcur, Vp);
+            else
+                row_step<R, N>(Mi, Ii, Mo, Io, hc, bidx, c, Mleft, Ileft, C, gprev, gcur, Vp);
+            // carries for the next row: left neighbour's last column, and the
+            // exclusive scan of the shifted window sums
+            Mleft = notstart * dpp<kWaveShr1>(Mo[N - 1]);
+            Ileft = notstart * dpp<kWaveShr1>(Io[N - 1]);
+            const R vsh = fmaR(gN1, Mleft, Vp);
+            C = seg_scan(notstart * dpp<kWaveShr1>(vsh), mul);
+        };
 
         for (int i0 = 0; i0 < l; i0 += kWave) {
             __syncthreads();
@@ -237,34 +276,20 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
                     rr.tii = (R)g;
                     rr.pm = (R)pm;
                     rec[lane] = rr;
-                    rinfo[lane] = read_class_mask(b.reads[a]) | (gc << 16);
+                    rinfo[lane] = read_base_index(b.reads[a]) | (gc << 16);
                 }
             }
             __syncthreads();
             const int nrows = l - i0 < kWave ? l - i0 : kWave;
-            for (int tt = 0; tt < nrows; ++tt) {
-                const RowRec<R> c = rec[tt];
-                const int info = __builtin_amdgcn_readfirstlane(rinfo[tt]);
-                if (varying) {
-                    const int gc = info >> 16;
-                    gprev = gcur;
-                    gcur = (R)t.p64[gc];
-                    const R* pwi = pow_table<R>(t, CLS, gc);
-                    mul = make_scan_mul<R>(pwi, lane, segstart);
-                    gN1 = pwi[65];
-                }
-                const int cmask = info & 0xffff;
-                R Vp;
-                if (i0 + tt == 0)
-                    row_first<R, N>(Mp, Ip, hv, cmask, c, minit, gcur, Vp);
-                else
-                    row_step<R, N>(Mp, Ip, hv, cmask, c, Mleft, Ileft, C, gprev, gcur, Vp);
-                // carries for the next row: left neighbour's last column, and
-                // the exclusive scan of the shifted window sums
-                Mleft = notstart * dpp<kWaveShr1>(Mp[N - 1]);
-                Ileft = notstart * dpp<kWaveShr1>(Ip[N - 1]);
-                const R vsh = fmaR(gN1, Mleft, Vp);
-                C = seg_scan(notstart * dpp<kWaveShr1>(vsh), mul);
+            int tt = 0;
+            for (; tt + 1 < nrows; tt += 2) {
+                do_row(tt, i0 + tt == 0, Ma, Ia, Mb, Ib);
+                do_row(tt + 1, false, Mb, Ib, Ma, Ia);
+            }
+            if (tt < nrows) {
+                do_row(tt, i0 + tt == 0, Ma, Ia, Mb, Ib);
+#pragma unroll
+                for (int n = 0; n < N; ++n) { Ma[n] = Mb[n]; Ia[n] = Ib[n]; }
             }
         }
 
@@ -272,7 +297,7 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
         R s = (R)0;
 #pragma unroll
         for (int n = 0; n < N; ++n)
-            if ((uint32_t)(c0 + n) < k) s += Mp[n] + Ip[n];
+            if ((uint32_t)(c0 + n) < k) s += Ma[n] + Ia[n];
         if (!real) s = (R)0;
         s = seg_scan(s, make_sum_mul<R>(lane, segstart));
 

@@ -268,3 +268,9 @@ def test_async_matches_sync(ctx32):
     assert np.array_equal(fl.cpu().numpy(), sync_fl)
     counts = phmm.phmm_last_counts(ctx32, ws)
     assert counts["packs_fp32"] > 0
+
+
+def test_vector_peak_calibration():
+    fp32, fp64 = phmm.phmm_vector_peak(0)
+    say("vector FMA peak: FP32 %.1f, FP64 %.1f TFLOP/s" % (fp32, fp64))
+    assert 10 < fp64 < 200 and 10 < fp32 < 400
