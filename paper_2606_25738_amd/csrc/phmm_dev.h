@@ -131,11 +131,15 @@ __device__ __forceinline__ float emit_sel(uint32_t w, int off, float pm, float p
     return __builtin_bit_cast(float, (m & __builtin_bit_cast(uint32_t, pm)) |
                                          (~m & __builtin_bit_cast(uint32_t, px)));
 }
+// The 32-bit mask is applied to each half of the doubles separately: hipcc
+// (ROCm 7.2) drops the upper half of a sign-extended 64-bit bfe mask.
 __device__ __forceinline__ double emit_sel(uint32_t w, int off, double pm, double px)
 {
-    const uint64_t m = (uint64_t)(int64_t)__builtin_amdgcn_sbfe((int)w, off, 1);
-    return __builtin_bit_cast(double, (m & __builtin_bit_cast(uint64_t, pm)) |
-                                          (~m & __builtin_bit_cast(uint64_t, px)));
+    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)w, off, 1);
+    const uint64_t a = __builtin_bit_cast(uint64_t, pm), b = __builtin_bit_cast(uint64_t, px);
+    const uint32_t lo = (m & (uint32_t)a) | (~m & (uint32_t)b);
+    const uint32_t hi = (m & (uint32_t)(a >> 32)) | (~m & (uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 __device__ __forceinline__ uint32_t wave_broadcast0(uint32_t x)
