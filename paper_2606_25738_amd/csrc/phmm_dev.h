@@ -142,6 +142,94 @@ __device__ __forceinline__ double emit_sel(uint32_t w, int off, double pm, doubl
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// ---------------------------------------------------------------- row recurrence
+//
+// Per-row coefficients, computed once per read row in FP64 and stored in LDS.
+// With PRE the insert row is kept pre-multiplied by the next row's T_IM
+// (I' = T_IM_{i+1} I), so the match update needs two FMAs instead of a
+// multiply and two FMAs; the insert update then uses
+// a = T_IM_{i+1} T_MI_i and b = T_IM_{i+1} T_II_i / T_IM_i (T_IM_{l+1} = 1, so
+// the last row holds I itself).  PRE needs T_IM_i > 0 on every row; without
+// it, a = T_MI_i and b = T_II_i.
+template <typename R>
+struct RowRec {
+    R pm, px, tmm, cd, a, b, tim, pad;
+};
+
+template <typename R, bool PRE>
+__device__ __forceinline__ RowRec<R> make_row_rec(const Batch& B, const double* p64, uint64_t a,
+                                                  int i, int l)
+{
+    const double eps = p64[B.bq[a]];
+    const double tmi = p64[B.iq[a]];
+    const double tmd = p64[B.dq[a]];
+    const double g = p64[B.gq[a]];
+    const double tmd_prev = i > 0 ? p64[B.dq[a - 1]] : 0.0;
+    double tmm = 1.0 - (tmi + tmd);
+    tmm = tmm < 0.0 ? 0.0 : tmm;
+    const double pm = 1.0 - eps, px = eps / 3.0, tim = 1.0 - g;
+    RowRec<R> r;
+    r.pm = (R)pm;
+    r.px = (R)px;
+    r.tmm = (R)tmm;
+    r.cd = (R)(tim * tmd_prev);  // T_DM_i T_MD_{i-1}
+    if (PRE) {
+        const double tim_next = i + 1 < l ? 1.0 - p64[B.gq[a + 1]] : 1.0;
+        r.a = (R)(tim_next * tmi);
+        r.b = (R)(tim_next * g / tim);
+    } else {
+        r.a = (R)tmi;
+        r.b = (R)g;
+    }
+    r.tim = (R)tim;
+    r.pad = (R)0;
+    return r;
+}
+
+// Row 1: M(1,j) = P(r_1|h_j) T_DM_1 C0/k, I(1,j) = 0.
+template <typename R, int N>
+__device__ __forceinline__ void row_first(R (&Mo)[N], R (&Io)[N], const uint32_t (&hc)[(N + 3) / 4],
+                                          int bidx, const RowRec<R>& c, R minit, R g, R& Vp)
+{
+    R V = (R)0;
+    const R base = c.tim * minit;  // T_DM_1 = T_IM_1
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const R p = emit_sel(hc[n / 4], 8 * (n % 4) + bidx, c.pm, c.px);
+        const R m = p * base;
+        Mo[n] = m;
+        Io[n] = (R)0;
+        if (n < N - 1) V = fmaR(g, V, m);
+    }
+    Vp = V;
+}
+
+// Rows 2..l of the row-level recurrence: reads row i-1 from (Mi, Ii) and
+// writes row i to (Mo, Io).  T rebuilds S(i-1, .) from the lane's carry C, V
+// accumulates the new row's window sum for the next scan.
+template <typename R, int N, bool PRE>
+__device__ __forceinline__ void row_step(const R (&Mi)[N], const R (&Ii)[N], R (&Mo)[N], R (&Io)[N],
+                                         const uint32_t (&hc)[(N + 3) / 4], int bidx,
+                                         const RowRec<R>& c, R Mleft, R Ileft, R C, R gprev,
+                                         R gcur, R& Vp)
+{
+    R T = C, V = (R)0;
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const R mprev = n == 0 ? Mleft : Mi[n - 1];
+        const R iprev = n == 0 ? Ileft : Ii[n - 1];
+        const R p = emit_sel(hc[n / 4], 8 * (n % 4) + bidx, c.pm, c.px);
+        const R x = PRE ? fmaR(c.cd, T, fmaR(c.tmm, mprev, iprev))
+                        : fmaR(c.cd, T, fmaR(c.tim, iprev, c.tmm * mprev));
+        const R m = p * x;
+        Mo[n] = m;
+        Io[n] = fmaR(c.b, Ii[n], c.a * Mi[n]);
+        T = fmaR(gprev, T, mprev);
+        if (n < N - 1) V = fmaR(gcur, V, m);
+    }
+    Vp = V;
+}
+
 __device__ __forceinline__ uint32_t wave_broadcast0(uint32_t x)
 {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);

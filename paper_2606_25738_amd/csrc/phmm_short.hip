@@ -29,14 +29,11 @@
 // Scale: D(0,j) = C0/k with C0 = 2^120 (FP32) or 2^1020 (FP64), eq.1.  The
 // FP32 instantiation tests each result against the acceptance threshold and
 // queues rejected pairs for the FP64 instantiation (precision policy).
+#include <type_traits>
+
 #include "phmm_dev.h"
 
 namespace phmm {
-
-template <typename R>
-struct RowRec {
-    R dp, px, tmm, tim, cd, tmi, tii, pm;
-};
 
 template <typename R>
 struct ScaleOf;
@@ -63,48 +60,6 @@ __device__ __forceinline__ const double* pow_table<double>(const Tables& t, int 
 }
 
 constexpr int words_for(int n) { return (n + 3) / 4; }
-
-// Row 1: M(1,j) = P(r_1|h_j) T_DM_1 C0/k, I(1,j) = 0.
-template <typename R, int N>
-__device__ __forceinline__ void row_first(R (&Mo)[N], R (&Io)[N], const uint32_t (&hc)[words_for(N)],
-                                          int bidx, const RowRec<R>& c, R minit, R g, R& Vp)
-{
-    R V = (R)0;
-    const R base = c.tim * minit;  // T_DM_1 = T_IM_1
-#pragma unroll
-    for (int n = 0; n < N; ++n) {
-        const R p = emit_sel(hc[n / 4], 8 * (n % 4) + bidx, c.pm, c.px);
-        const R m = p * base;
-        Mo[n] = m;
-        Io[n] = (R)0;
-        if (n < N - 1) V = fmaR(g, V, m);
-    }
-    Vp = V;
-}
-
-// Rows 2..l of the row-level recurrence (see the file comment); reads row
-// i-1 from (Mi, Ii) and writes row i to (Mo, Io).
-template <typename R, int N>
-__device__ __forceinline__ void row_step(const R (&Mi)[N], const R (&Ii)[N], R (&Mo)[N], R (&Io)[N],
-                                         const uint32_t (&hc)[words_for(N)], int bidx,
-                                         const RowRec<R>& c, R Mleft, R Ileft, R C, R gprev,
-                                         R gcur, R& Vp)
-{
-    R T = C, V = (R)0;
-#pragma unroll
-    for (int n = 0; n < N; ++n) {
-        const R mprev = n == 0 ? Mleft : Mi[n - 1];
-        const R iprev = n == 0 ? Ileft : Ii[n - 1];
-        const R p = emit_sel(hc[n / 4], 8 * (n % 4) + bidx, c.pm, c.px);
-        const R x = fmaR(c.cd, T, fmaR(c.tim, iprev, c.tmm * mprev));
-        const R m = p * x;
-        Mo[n] = m;
-        Io[n] = fmaR(c.tii, Ii[n], c.tmi * Mi[n]);
-        T = fmaR(gprev, T, mprev);
-        if (n < N - 1) V = fmaR(gcur, V, m);
-    }
-    Vp = V;
-}
 
 // FP32 instantiation: walks the FP32 packs of class CLS and queues rejected
 // pairs as FP64 items.  FP64 instantiation: walks the FP64 items of class
@@ -206,11 +161,12 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
         const uint64_t roff = b.read_off[r];
         const int l = (int)(b.read_off[r + 1] - roff);
         const int g0 = b.gq[roff];
-        bool varying = false;
+        bool varying = false, tim_zero = false;
         for (int i0 = 0; i0 < l; i0 += kWave) {
             const int i = i0 + lane;
-            const bool d = i < l && (int)b.gq[roff + i] != g0;
-            if (__ballot(d) != 0ull) { varying = true; break; }
+            const int gc = i < l ? (int)b.gq[roff + i] : g0;
+            varying = varying || __ballot(gc != g0) != 0ull;
+            tim_zero = tim_zero || __ballot(gc == 0) != 0ull;  // g = 1: T_IM = 0
         }
         const R notstart = (lane != segstart) ? (R)1 : (R)0;
         const R minit = real ? (R)(ldexp(1.0, ScaleOf<R>::exp) / (double)k) : (R)0;
@@ -223,75 +179,65 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
         for (int n = 0; n < N; ++n) { Ma[n] = (R)0; Ia[n] = (R)0; }
         R Mleft = (R)0, Ileft = (R)0, C = (R)0;
 
-        // one row of the recurrence plus the carries for the next row; rows
-        // alternate between the (Ma, Ia) and (Mb, Ib) register sets
-        auto do_row = [&](int tt, bool first, const R(&Mi)[N], const R(&Ii)[N], R(&Mo)[N],
-                          R(&Io)[N]) {
-            const RowRec<R> c = rec[tt];
-            const int info = __builtin_amdgcn_readfirstlane(rinfo[tt]);
-            if (varying) {
-                const int gc = info >> 16;
-                gprev = gcur;
-                gcur = (R)t.p64[gc];
-                const R* pwi = pow_table<R>(t, CLS, gc);
-                mul = make_scan_mul<R>(pwi, lane, segstart);
-                gN1 = pwi[65];
-            }
-            const int bidx = info & 0xff;
-            R Vp;
-            if (first)
-                row_first<R, N>(Mo, Io, hc, bidx, c, minit, gcur, Vp);
-            else
-                row_step<R, N>(Mi, Ii, Mo, Io, hc, bidx, c, Mleft, Ileft, C, gprev, gcur, Vp);
-            // carries for the next row: left neighbour's last column, and the
-            // exclusive scan of the shifted window sums
-            Mleft = notstart * dpp<kWaveShr1>(Mo[N - 1]);
-            Ileft = notstart * dpp<kWaveShr1>(Io[N - 1]);
-            const R vsh = fmaR(gN1, Mleft, Vp);
-            C = seg_scan(notstart * dpp<kWaveShr1>(vsh), mul);
-        };
-
-        for (int i0 = 0; i0 < l; i0 += kWave) {
-            __syncthreads();
-            {   // priors of rows i0 .. i0+63 (eq.3 and the transition priors)
-                const int i = i0 + lane;
-                if (i < l) {
-                    const uint64_t a = roff + (uint64_t)i;
-                    const double eps = t.p64[b.bq[a]];
-                    const double tmi = t.p64[b.iq[a]];
-                    const double tmd_prev = i > 0 ? t.p64[b.dq[a - 1]] : 0.0;
-                    const int gc = b.gq[a];
-                    const double g = t.p64[gc];
-                    const double tmd = t.p64[b.dq[a]];
-                    double tmm = 1.0 - (tmi + tmd);
-                    tmm = tmm < 0.0 ? 0.0 : tmm;
-                    const double pm = 1.0 - eps, px = eps / 3.0, tim = 1.0 - g;
-                    RowRec<R> rr;
-                    rr.dp = (R)(pm - px);
-                    rr.px = (R)px;
-                    rr.tmm = (R)tmm;
-                    rr.tim = (R)tim;
-                    rr.cd = (R)(tim * tmd_prev);
-                    rr.tmi = (R)tmi;
-                    rr.tii = (R)g;
-                    rr.pm = (R)pm;
-                    rec[lane] = rr;
-                    rinfo[lane] = read_base_index(b.reads[a]) | (gc << 16);
+        // all rows of the pack; PRE selects the pre-scaled insert row
+        auto run_rows = [&](auto pre_tag) {
+            constexpr bool PRE = decltype(pre_tag)::value;
+            // one row of the recurrence plus the carries for the next row;
+            // rows alternate between the (Ma, Ia) and (Mb, Ib) register sets
+            auto do_row = [&](int tt, bool first, const R(&Mi)[N], const R(&Ii)[N], R(&Mo)[N],
+                              R(&Io)[N]) {
+                const RowRec<R> c = rec[tt];
+                const int info = __builtin_amdgcn_readfirstlane(rinfo[tt]);
+                if (varying) {
+                    const int gc = info >> 16;
+                    gprev = gcur;
+                    gcur = (R)t.p64[gc];
+                    const R* pwi = pow_table<R>(t, CLS, gc);
+                    mul = make_scan_mul<R>(pwi, lane, segstart);
+                    gN1 = pwi[65];
+                }
+                const int bidx = info & 0xff;
+                R Vp;
+                if (first)
+                    row_first<R, N>(Mo, Io, hc, bidx, c, minit, gcur, Vp);
+                else
+                    row_step<R, N, PRE>(Mi, Ii, Mo, Io, hc, bidx, c, Mleft, Ileft, C, gprev,
+                                        gcur, Vp);
+                // carries for the next row: left neighbour's last column, and
+                // the exclusive scan of the shifted window sums
+                Mleft = notstart * dpp<kWaveShr1>(Mo[N - 1]);
+                Ileft = notstart * dpp<kWaveShr1>(Io[N - 1]);
+                const R vsh = fmaR(gN1, Mleft, Vp);
+                C = seg_scan(notstart * dpp<kWaveShr1>(vsh), mul);
+            };
+            for (int i0 = 0; i0 < l; i0 += kWave) {
+                __syncthreads();
+                {   // priors of rows i0 .. i0+63 (eq.3 and the transition priors)
+                    const int i = i0 + lane;
+                    if (i < l) {
+                        const uint64_t a = roff + (uint64_t)i;
+                        rec[lane] = make_row_rec<R, PRE>(b, t.p64, a, i, l);
+                        rinfo[lane] = read_base_index(b.reads[a]) | ((int)b.gq[a] << 16);
+                    }
+                }
+                __syncthreads();
+                const int nrows = l - i0 < kWave ? l - i0 : kWave;
+                int tt = 0;
+                for (; tt + 1 < nrows; tt += 2) {
+                    do_row(tt, i0 + tt == 0, Ma, Ia, Mb, Ib);
+                    do_row(tt + 1, false, Mb, Ib, Ma, Ia);
+                }
+                if (tt < nrows) {
+                    do_row(tt, i0 + tt == 0, Ma, Ia, Mb, Ib);
+#pragma unroll
+                    for (int n = 0; n < N; ++n) { Ma[n] = Mb[n]; Ia[n] = Ib[n]; }
                 }
             }
-            __syncthreads();
-            const int nrows = l - i0 < kWave ? l - i0 : kWave;
-            int tt = 0;
-            for (; tt + 1 < nrows; tt += 2) {
-                do_row(tt, i0 + tt == 0, Ma, Ia, Mb, Ib);
-                do_row(tt + 1, false, Mb, Ib, Ma, Ia);
-            }
-            if (tt < nrows) {
-                do_row(tt, i0 + tt == 0, Ma, Ia, Mb, Ib);
-#pragma unroll
-                for (int n = 0; n < N; ++n) { Ma[n] = Mb[n]; Ia[n] = Ib[n]; }
-            }
-        }
+        };
+        if (tim_zero)
+            run_rows(std::false_type{});
+        else
+            run_rows(std::true_type{});
 
         // ---- eq.4: S = sum_j M(l,j) + I(l,j) over the real columns
         R s = (R)0;
