@@ -22,9 +22,9 @@
 // no division by T_DD (the paper's T_DD^-1 (T - V) step) is required.
 //
 // Emission (eq.3): every pack holds one read, so r_i is wavefront-uniform.
-// Haplotype columns are held as floats whose IEEE class names the base; one
-// class test against the row's class mask selects pm = 1 - eps or
-// px = eps / 3 for each column, with 'N' on either side matching any base.
+// Haplotype columns are held as 8-bit match codes (four per register); the
+// row's read-base index selects one bit per column, which picks pm = 1 - eps
+// or px = eps / 3 bit-wise, with 'N' on either side matching any base.
 //
 // Scale: D(0,j) = C0/k with C0 = 2^120 (FP32) or 2^1020 (FP64), eq.1.  The
 // FP32 instantiation tests each result against the acceptance threshold and
