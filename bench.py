@@ -13,10 +13,14 @@ Prints one JSON line (see the design notes for every field).
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import math
 import multiprocessing as mp
 import os
+import re
 import sys
 import time
 
@@ -32,6 +36,12 @@ FLOPS_PER_CELL = 12          # eq.2 as written, an FMA counted as two flops
 FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32 (vendor figure)
 
 _BATCH = None  # inherited by the oracle worker processes
+
+# HBM traffic of the FP32 short-kernel family, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs of this script (see summarize_traffic); valid only for the
+# kernel sources and workload it was taken on.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_short_fp32_wgs.md")
+CSRC = os.path.join(ROOT, "paper_2606_25738_amd", "csrc")
 
 
 def log(*a):
@@ -64,6 +74,80 @@ def run_oracle(batch, idx, cores):
     vals = np.concatenate([r[0] for r in res])
     cpu = sum(r[1] for r in res)
     return vals, wall, cpu
+
+
+def sources_digest():
+    """sha256 over the kernel sources (any change invalidates stored counters)."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(CSRC, "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _pmc_rows(path, counter):
+    with open(path, newline="") as fh:
+        return [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+
+
+def summarize_traffic(fetch_csv, write_csv, out_path, regions, calib_mib, commands):
+    """Writes the traffic profile from two rocprofv3 --pmc runs (FETCH_SIZE,
+    then WRITE_SIZE) of `bench.py --steps 1 --warmup 0 --fp64-steps 0 --no-cpu`.
+
+    Counter values are KiB per dispatch.  Each counter is scaled by the ratio
+    of the known size of the calibration copy (calib_mib read, calib_mib
+    written) to what the same counter reads for that copy kernel."""
+    res = {}
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = _pmc_rows(path, name)
+        calib = [float(r["Counter_Value"]) for r in rows if "copy_calib_kernel" in r["Kernel_Name"]]
+        if not calib:
+            raise SystemExit("no copy_calib_kernel dispatch in %s" % path)
+        factor = calib_mib * 1024.0 / calib[-1]
+        per = {}
+        for r in rows:
+            m = re.search(r"short_kernel<float, (\d+)>", r["Kernel_Name"])
+            if m:
+                per[int(m.group(1))] = per.get(int(m.group(1)), 0.0) + float(r["Counter_Value"])
+        res[name] = dict(factor=factor, calib_kib=calib[-1], per_class=per)
+    f, w = res["FETCH_SIZE"], res["WRITE_SIZE"]
+    fetch_b = sum(f["per_class"].values()) * 1024.0 * f["factor"]
+    write_b = sum(w["per_class"].values()) * 1024.0 * w["factor"]
+    lines = ["# HBM traffic of the FP32 short-pair kernels, genome-scale WGS-like batch", "",
+             "Commands (repository root, one MI355X):", ""]
+    lines += ["    " + c for c in commands]
+    lines += ["", "Workload: %d regions, one step (11 launches of `short_kernel<float, c>`)." % regions,
+              "Counters are KiB per dispatch. Scale factor = known bytes of the calibration copy",
+              "(`copy_calib_kernel`, %d MiB read and %d MiB written) / the counter's reading for it." %
+              (calib_mib, calib_mib), "",
+              "| class c (N = 4 + 2c) | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---:|---:|---:|"]
+    for c in sorted(set(f["per_class"]) | set(w["per_class"])):
+        lines.append("| %d | %.1f | %.1f |" % (c, f["per_class"].get(c, 0.0), w["per_class"].get(c, 0.0)))
+    lines += ["", "Calibration copy: FETCH_SIZE %.1f KiB, WRITE_SIZE %.1f KiB for %d KiB each way." %
+              (f["calib_kib"], w["calib_kib"], calib_mib * 1024),
+              "", "Values read by bench.py:", "",
+              "- regions: %d" % regions,
+              "- fetch_factor: %.6f" % f["factor"],
+              "- write_factor: %.6f" % w["factor"],
+              "- fetch_bytes_per_step: %.6e" % fetch_b,
+              "- write_bytes_per_step: %.6e" % write_b,
+              "- traffic_bytes_per_step: %.6e" % (fetch_b + write_b),
+              "- sources_sha256: %s" % sources_digest(), ""]
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+def stored_traffic(regions):
+    """Bytes per step of the FP32 short-kernel family from the committed
+    profile, or None if it was taken on other sources or another workload."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    vals = dict(re.findall(r"^- (\w+): (\S+)$", open(TRAFFIC_PROFILE).read(), flags=re.M))
+    if vals.get("sources_sha256") != sources_digest() or int(vals.get("regions", -1)) != regions:
+        return None
+    return float(vals["traffic_bytes_per_step"])
 
 
 def pair_cells(batch):
@@ -104,7 +188,17 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1,
                     help="timed steps of the plain FP64 path on the same batch (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=1024,
+                    help="size of the calibration copy run before the timed steps")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic profile from two rocprofv3 --pmc runs (no GPU used)")
+    ap.add_argument("--command", action="append", default=[],
+                    help="with --summarize-traffic: a command line to record in the profile")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(args.summarize_traffic[0], args.summarize_traffic[1], TRAFFIC_PROFILE,
+                          args.regions, args.calib_copy_mib, args.command)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only; this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -149,6 +243,21 @@ def main():
     ctx = phmm.Context(timing=True)
     ws = torch.empty(phmm.phmm_workspace_bytes(ctx, n_pairs, db.max_read_len, db.max_hap_len),
                      dtype=torch.uint8, device="cuda:0")
+    copy_gbs = None
+    if args.calib_copy_mib > 0:
+        # plain copy of known size: the reference for the traffic counters
+        nb = args.calib_copy_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            phmm.phmm_copy_calib(src, dst, stream)
+            e1.record(stream)
+        e1.synchronize()
+        copy_gbs = 2.0 * nb / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del src, dst
+        log("calibration copy: %d MiB, %.0f GB/s" % (args.calib_copy_mib, copy_gbs))
     elapsed, ph = time_steps(phmm, torch, ctx, db, out, fl, ws, stream, args.warmup, args.steps)
     counts = phmm.phmm_last_counts(ctx, ws)
     ms_per_step = elapsed * 1000.0 / args.steps
@@ -159,9 +268,17 @@ def main():
     # dominant kernel: the FP32 short-pair kernels (one launch per column class)
     short = (hl <= 64 * 24)
     cells32 = int(cells_pp[short].sum())
+    # algorithmic HBM bytes of the short pairs, per pair: the five per-base read
+    # arrays, the haplotype, and 9 output bytes (log10 L and the flag)
+    alg_bytes = float((5 * rl[short] + hl[short] + 9).sum())
     achieved = FLOPS_PER_CELL * cells32 / (ph["short_ms"] / 1e3) / 1e12
+    traffic = stored_traffic(args.regions)
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                frac=round(achieved / FP32_PEAK_TFLOPS, 4), traffic=None,
+                frac=round(achieved / FP32_PEAK_TFLOPS, 4),
+                traffic=None if traffic is None else round(traffic),
+                traffic_unit="bytes per step (11 launches)",
+                algorithmic_bytes=int(alg_bytes), hbm_gbs_from_traffic=None if traffic is None
+                else round(traffic / (ph["short_ms"] / 1e3) / 1e9, 2), copy_calib_gbs=copy_gbs,
                 kernel="FP32 short-pair kernels (11 column-class launches per step)",
                 kernel_ms=round(ph["short_ms"], 3),
                 measured_peak_fp32=round(peak32, 2), measured_peak_fp64=round(peak64, 2),

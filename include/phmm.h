@@ -240,6 +240,16 @@ int phmm_last_timing(phmm_ctx* ctx, phmm_timing* out);
  * PHMM_EDEVICE. */
 int phmm_vector_peak(int device, double* fp32_tflops, double* fp64_tflops);
 
+/* Calibration: copies `bytes` bytes from device buffer `src` to device buffer
+ * `dst` on `stream` (a hipStream_t, NULL = default stream) with a plain
+ * vector copy kernel (`copy_calib_kernel`).  Its hardware traffic counters
+ * read against the known 2 x bytes give the scale factor applied to the
+ * traffic counters of the PairHMM kernels in a profile.  Both pointers and
+ * `bytes` must be multiples of 16 and the buffers must not overlap; the call
+ * is stream-ordered and does not synchronise.  Errors: PHMM_EINVAL (NULL or
+ * misaligned arguments), PHMM_EDEVICE (launch failure). */
+int phmm_copy_calib(const void* src, void* dst, uint64_t bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

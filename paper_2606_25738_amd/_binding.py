@@ -106,6 +106,8 @@ def lib():
             L.phmm_last_timing.argtypes = [vp, ctypes.POINTER(_Timing)]
             L.phmm_vector_peak.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double)]
+            L.phmm_copy_calib.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                          ctypes.c_void_p]
             _lib = L
     return _lib
 
@@ -300,6 +302,16 @@ def phmm_vector_peak(device: int = 0) -> tuple[float, float]:
     a, b = ctypes.c_double(0.0), ctypes.c_double(0.0)
     _check(lib().phmm_vector_peak(device, ctypes.byref(a), ctypes.byref(b)))
     return a.value, b.value
+
+
+def phmm_copy_calib(src, dst, stream=None) -> None:
+    """Plain device copy of src into dst (torch uint8 device tensors of equal
+    size), the reference kernel of traffic-counter calibration."""
+    if src.numel() != dst.numel() or src.element_size() != 1 or dst.element_size() != 1:
+        raise ValueError("phmm_copy_calib: src and dst must be byte tensors of equal size")
+    s = stream.cuda_stream if stream is not None else None
+    _check(lib().phmm_copy_calib(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                 src.numel(), ctypes.c_void_p(s)))
 
 
 def phmm_last_timing(ctx: Context) -> dict:

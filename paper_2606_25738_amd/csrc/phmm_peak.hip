@@ -1,4 +1,6 @@
-// Vector-ALU FMA rate microbenchmark (calibration of the roofline peak).
+// Calibration kernels: the vector-ALU FMA rate (the roofline peak) and a
+// plain device copy of known size (the reference that scales the HBM traffic
+// counters of a profile).
 //
 // Every lane runs 16 independent FMA chains; with enough wavefronts per SIMD
 // the VALU issue rate, not latency, bounds the run.  Packed FP32 forms are
@@ -59,7 +61,31 @@ double run(int cus, int iters)
     return tflops;
 }
 
+// Plain copy, 16 bytes per lane per step, grid-stride.
+__global__ __launch_bounds__(256) void copy_calib_kernel(const uint4* __restrict__ src,
+                                                         uint4* __restrict__ dst, uint64_t n16)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        dst[i] = src[i];
+}
+
 }  // namespace
+
+extern "C" int phmm_copy_calib(const void* src, void* dst, uint64_t bytes, void* stream)
+{
+    if (!src || !dst || (bytes & 15u) != 0 || ((uintptr_t)src & 15u) != 0 ||
+        ((uintptr_t)dst & 15u) != 0)
+        return PHMM_EINVAL;
+    if (bytes == 0) return PHMM_OK;
+    const uint64_t n16 = bytes / 16;
+    uint64_t blocks = (n16 + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(copy_calib_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), static_cast<const uint4*>(src),
+                       static_cast<uint4*>(dst), n16);
+    return hipGetLastError() == hipSuccess ? PHMM_OK : PHMM_EDEVICE;
+}
 
 extern "C" int phmm_vector_peak(int device, double* fp32_tflops, double* fp64_tflops)
 {
