@@ -150,6 +150,96 @@ def stored_traffic(regions):
     return float(vals["traffic_bytes_per_step"])
 
 
+def _percentiles(x):
+    if len(x) == 0:
+        return None
+    x = np.asarray(x) * 1e3
+    return dict(n=int(len(x)), p50_ms=round(float(np.percentile(x, 50)), 3),
+                p99_ms=round(float(np.percentile(x, 99)), 3), max_ms=round(float(x.max()), 3))
+
+
+def serve_leg(phmm, args):
+    """The served request stream: regions of the mixed workload (95% short,
+    5% long-read regions) arrive Poisson at a fixed rate; the server batches
+    them continuously.  First the sustainable capacity is measured by
+    submitting a block of regions at once, then the stream runs at
+    args.serve_load times that capacity for args.serve_seconds."""
+    import threading
+    gen_chunk = 2000
+    cache = {}
+
+    def region(i):
+        c = i // gen_chunk
+        if c not in cache:
+            cache[c] = synth.generate("cfg4", c * gen_chunk, gen_chunk)
+        return synth.region_slice(cache[c], i - c * gen_chunk)
+
+    opts = dict(lanes=args.serve_lanes, long_lanes=1, hbm_budget_bytes=args.serve_budget_gib << 30,
+                short_cu_percent=args.serve_short_cu)
+    with phmm.Server(**opts) as srv:
+        # capacity: a block submitted at once
+        n_cap = args.serve_capacity_regions
+        regs = [region(i) for i in range(n_cap)]
+        t0 = time.perf_counter()
+        ts = [srv.submit(r) for r in regs]
+        cap_cells = 0
+        for t in ts:
+            _, _, info = srv.wait(t)
+            cap_cells += info["cells"]
+        span = time.perf_counter() - t0
+        cap_rps = n_cap / span
+        log("serving capacity: %d regions, %.3g cells in %.2f s -> %.1f regions/s, %.1f GCUPS"
+            % (n_cap, cap_cells, span, cap_rps, cap_cells / span / 1e9))
+        del regs
+        cache.clear()
+        # the stream (all its regions generated before the clock starts)
+        rate = args.serve_load * cap_rps
+        rng = np.random.default_rng(4)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * args.serve_seconds * 1.2) + 10))
+        arrivals = arrivals[arrivals < args.serve_seconds]
+        n = len(arrivals)
+        regs = [region(n_cap + q) for q in range(n)]
+        tickets = [None] * n
+        late = [0.0]
+
+        def submitter():
+            base = time.perf_counter()
+            for q in range(n):
+                r = regs[q]
+                d = base + arrivals[q] - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                else:
+                    late[0] = max(late[0], -d)
+                tickets[q] = srv.submit(r)
+        th = threading.Thread(target=submitter)
+        ts0 = time.perf_counter()
+        th.start()
+        lat, lat_s, lat_l, cells = [], [], [], 0
+        for q in range(n):
+            while tickets[q] is None:
+                time.sleep(0.0002)
+            _, _, info = srv.wait(tickets[q])
+            lat.append(info["latency_s"])
+            (lat_l if info["is_long"] else lat_s).append(info["latency_s"])
+            cells += info["cells"]
+        th.join()
+        wall = time.perf_counter() - ts0
+        st = srv.stats()
+    res = dict(arrival="poisson", rate_regions_per_s=round(rate, 2), load=args.serve_load,
+               capacity_regions_per_s=round(cap_rps, 2),
+               capacity_gcups=round(cap_cells / span / 1e9, 2), seconds=args.serve_seconds,
+               regions=n, cells=cells, gcups=round(cells / wall / 1e9, 2),
+               latency_all=_percentiles(lat), latency_short=_percentiles(lat_s),
+               latency_long=_percentiles(lat_l), batches=int(st["batches"]),
+               full_batches=int(st["full_batches"]), max_submit_lag_ms=round(late[0] * 1e3, 3),
+               lanes=args.serve_lanes, long_lanes=1, short_cu_percent=args.serve_short_cu,
+               cu_mask_status=int(st["cu_mask_status"]), budget_gib=args.serve_budget_gib)
+    log("served stream: %d regions at %.1f/s, p50 %.2f ms, p99 %.2f ms, %.1f GCUPS"
+        % (n, rate, res["latency_all"]["p50_ms"], res["latency_all"]["p99_ms"], res["gcups"]))
+    return res
+
+
 def pair_cells(batch):
     rl = np.diff(batch["read_offsets"]).astype(np.int64)
     hl = np.diff(batch["hap_offsets"]).astype(np.int64)
@@ -188,6 +278,15 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1,
                     help="timed steps of the plain FP64 path on the same batch (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="length of the served Poisson stream (0 = no serving leg)")
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="arrival rate as a fraction of the measured serving capacity")
+    ap.add_argument("--serve-capacity-regions", type=int, default=3000)
+    ap.add_argument("--serve-lanes", type=int, default=3)
+    ap.add_argument("--serve-budget-gib", type=int, default=24)
+    ap.add_argument("--serve-short-cu", type=int, default=0,
+                    help="percent of CUs for the short lanes (0 = no CU masks)")
     ap.add_argument("--calib-copy-mib", type=int, default=1024,
                     help="size of the calibration copy run before the timed steps")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -295,6 +394,8 @@ def main():
                     speedup_fp32_rerun=round(value / (cells / (e64 / args.fp64_steps) / 1e9), 3))
         ctx64.close()
 
+    serving = serve_leg(phmm, args) if args.serve_seconds > 0 else None
+
     parity = None
     if cpu is not None:
         g = out_h[sidx]
@@ -322,7 +423,7 @@ def main():
         phases_ms={k: round(v, 3) for k, v in ph.items()},
         rerun_pairs=int(counts["rerun_pairs"]), rerun_fraction=counts["rerun_pairs"] / max(1, n_pairs),
         lane_utilisation=round(cells32 / max(1, counts["lane_columns"] * 150), 4),
-        fp64_plain=fp64, parity_sample=parity,
+        fp64_plain=fp64, parity_sample=parity, serving=serving,
     )
     print(json.dumps(rec), flush=True)
 

@@ -67,6 +67,7 @@ extern "C" {
 #define PHMM_ENOMEM (-3)   /* device or host allocation failed, or workspace too small   */
 #define PHMM_EDEVICE (-4)  /* HIP error, or no gfx950 device                             */
 #define PHMM_ETIMEOUT (-5) /* long-pair kernel watchdog fired                            */
+#define PHMM_PENDING 1     /* phmm_server_poll: the region has not completed yet         */
 
 #define PHMM_MAX_READ 131072u
 #define PHMM_MAX_HAP (1u << 20)
@@ -249,6 +250,99 @@ int phmm_vector_peak(int device, double* fp32_tflops, double* fp64_tflops);
  * is stream-ordered and does not synchronise.  Errors: PHMM_EINVAL (NULL or
  * misaligned arguments), PHMM_EDEVICE (launch failure). */
 int phmm_copy_calib(const void* src, void* dst, uint64_t bytes, void* stream);
+
+/*
+ * Serving: a request loop with continuous batching.
+ *
+ * A server accepts active regions (the reads, haplotypes and pairs of one
+ * region, in the layout of phmm_forward_batch) from any host thread and
+ * returns each region's log10 likelihoods when they are done.  Regions that
+ * arrive while others are on the GPU are batched and launched as lanes free
+ * up, so their work overlaps on the device; a region's inputs and results stay
+ * resident in device memory for its whole pass.  The results are those of
+ * phmm_forward_batch on the region alone, up to the rounding differences a
+ * different position in a wavefront may cause (within the FP32 tolerance).
+ *
+ * Memory: hbm_budget_bytes of device memory (and as much pinned host memory)
+ * are divided evenly over the lanes at creation; a lane admits waiting
+ * regions in arrival order while the batch layout (inputs, outputs and
+ * workspace) fits its share.  A region too large for one lane is rejected at
+ * submission with PHMM_ENOMEM.
+ *
+ * Long regions (a haplotype longer than 64 x 24 columns or a read longer than
+ * 2048 bases) queue apart and run on the long_lanes last lanes when
+ * long_lanes > 0; with short_cu_percent in 1..99 the short lanes' streams are
+ * restricted to that share of the compute units and the long lanes' to the
+ * rest (CU masks; if the device refuses a mask the lanes run unrestricted and
+ * phmm_server_stats reports it).
+ */
+typedef struct phmm_server phmm_server;
+
+typedef struct phmm_server_options {
+    int precision;              /* PHMM_FP32_RERUN (default) or PHMM_FP64_PLAIN        */
+    uint32_t lanes;             /* batches in flight, one stream each; 1..16, default 3 */
+    uint32_t long_lanes;        /* lanes reserved for long regions (< lanes); default 1 */
+    uint64_t hbm_budget_bytes;  /* device bytes for admitted work; default 24 GiB       */
+    uint32_t max_batch_regions; /* regions per batch at most; default 8192              */
+    uint32_t short_cu_percent;  /* 0 = no CU masks; else the short lanes' CU share      */
+} phmm_server_options;
+
+typedef struct phmm_request_info {
+    uint64_t n_pairs, cells;    /* the region's pairs and DP cells                      */
+    uint32_t lane, is_long;     /* lane that ran it; 1 if it queued as a long region    */
+    uint64_t batch;             /* batch sequence number                                */
+    double queue_s;             /* submission to the start of its batch, seconds        */
+    double latency_s;           /* submission to completion, seconds                    */
+} phmm_request_info;
+
+typedef struct phmm_server_counters {
+    uint64_t regions, pairs, cells;  /* completed so far                                 */
+    uint64_t batches;                /* batches run                                      */
+    uint64_t full_batches;           /* batches that left waiting regions behind (budget
+                                        or max_batch_regions reached)                    */
+    uint64_t waiting_short, waiting_long;  /* regions queued now                        */
+    double lane_busy_s;              /* summed over lanes: batch start to completion     */
+    double span_s;                   /* first submission to last completion              */
+    int cu_mask_status;              /* 0 no masks asked, 1 applied, < 0 refused         */
+} phmm_server_counters;
+
+void phmm_server_default_options(phmm_server_options* opt);
+
+/* Creates a server on `device` (opt NULL = defaults): allocates the lanes'
+ * device and pinned host blocks and starts one worker thread per lane.
+ * Errors: PHMM_EINVAL (bad options), PHMM_ENOMEM, PHMM_EDEVICE. */
+int phmm_server_create(phmm_server** out, int device, const phmm_server_options* opt);
+
+/* Finishes every submitted region, stops the workers and frees everything.
+ * Results not collected are dropped.  NULL is ignored. */
+void phmm_server_destroy(phmm_server* srv);
+
+/* Submits one region (arguments as in phmm_forward_batch, n_pairs >= 1);
+ * the inputs are validated and copied before it returns, so the caller may
+ * reuse its buffers.  *ticket identifies the region in wait/poll.
+ * Errors: PHMM_EINVAL / PHMM_ERANGE (validation, as phmm_forward_batch),
+ * PHMM_ENOMEM (region larger than one lane's share of the budget). */
+int phmm_server_submit(phmm_server* srv, const uint8_t* reads, const uint8_t* base_quals,
+                       const uint8_t* ins_quals, const uint8_t* del_quals, const uint8_t* gcp,
+                       const uint64_t* read_offsets, uint32_t n_reads,
+                       const uint8_t* haplotypes, const uint64_t* hap_offsets, uint32_t n_haps,
+                       const uint32_t* pair_list, uint64_t n_pairs, uint64_t* ticket);
+
+/* Blocks until region `ticket` is done, then copies its n_pairs results
+ * (out_log10, out_flags; either may be NULL) and its info (may be NULL) and
+ * forgets the ticket.  Returns the region's status: PHMM_OK, or the error of
+ * its batch (PHMM_EDEVICE, PHMM_ETIMEOUT).  PHMM_EINVAL for an unknown
+ * ticket. */
+int phmm_server_wait(phmm_server* srv, uint64_t ticket, double* out_log10, uint8_t* out_flags,
+                     phmm_request_info* info);
+
+/* As phmm_server_wait, but returns PHMM_PENDING at once if the region is not
+ * done yet (the ticket stays valid). */
+int phmm_server_poll(phmm_server* srv, uint64_t ticket, double* out_log10, uint8_t* out_flags,
+                     phmm_request_info* info);
+
+/* Counters of the server since creation.  Errors: PHMM_EINVAL. */
+int phmm_server_stats(phmm_server* srv, phmm_server_counters* stats);
 
 #ifdef __cplusplus
 }

@@ -8,7 +8,7 @@ needs the built library and a gfx950 device and raises otherwise.
 from ._binding import (  # noqa: F401
     PHMM_OK, PHMM_EINVAL, PHMM_ERANGE, PHMM_ENOMEM, PHMM_EDEVICE, PHMM_ETIMEOUT,
     PHMM_FP32_RERUN, PHMM_FP64_PLAIN, PHMM_FLAG_FP32, PHMM_FLAG_RERUN, PHMM_FLAG_LONG,
-    PHMM_FLAG_RESCALED, PHMM_FLAG_FP64, PhmmError, Context, lib, lib_path,
+    PHMM_FLAG_RESCALED, PHMM_FLAG_FP64, PHMM_PENDING, PhmmError, Context, Server, lib, lib_path,
     phmm_num_classes, phmm_class_n, phmm_validate_batch, phmm_forward_batch,
     phmm_forward_one, phmm_workspace_bytes, phmm_forward_batch_async, phmm_device_status,
     phmm_last_counts, phmm_last_timing, phmm_vector_peak, phmm_copy_calib, DeviceBatch,

@@ -17,6 +17,7 @@ PHMM_ERANGE = -2
 PHMM_ENOMEM = -3
 PHMM_EDEVICE = -4
 PHMM_ETIMEOUT = -5
+PHMM_PENDING = 1
 PHMM_FP32_RERUN = 0
 PHMM_FP64_PLAIN = 1
 PHMM_FLAG_FP32 = 0x01
@@ -56,6 +57,27 @@ class _Counts(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("packs_fp32", "packs_fp64", "rerun_items",
                                                 "rerun_pairs", "long_pairs", "long_tiles",
                                                 "lane_columns")]
+
+
+class _ServerOptions(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("lanes", ctypes.c_uint32),
+                ("long_lanes", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64),
+                ("max_batch_regions", ctypes.c_uint32), ("short_cu_percent", ctypes.c_uint32)]
+
+
+class _RequestInfo(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_uint64), ("cells", ctypes.c_uint64),
+                ("lane", ctypes.c_uint32), ("is_long", ctypes.c_uint32),
+                ("batch", ctypes.c_uint64), ("queue_s", ctypes.c_double),
+                ("latency_s", ctypes.c_double)]
+
+
+class _ServerCounters(ctypes.Structure):
+    _fields_ = [("regions", ctypes.c_uint64), ("pairs", ctypes.c_uint64),
+                ("cells", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("full_batches", ctypes.c_uint64), ("waiting_short", ctypes.c_uint64),
+                ("waiting_long", ctypes.c_uint64), ("lane_busy_s", ctypes.c_double),
+                ("span_s", ctypes.c_double), ("cu_mask_status", ctypes.c_int)]
 
 
 class _Timing(ctypes.Structure):
@@ -108,6 +130,20 @@ def lib():
                                            ctypes.POINTER(ctypes.c_double)]
             L.phmm_copy_calib.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                           ctypes.c_void_p]
+            L.phmm_server_default_options.argtypes = [ctypes.POINTER(_ServerOptions)]
+            L.phmm_server_default_options.restype = None
+            L.phmm_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int,
+                                             ctypes.POINTER(_ServerOptions)]
+            L.phmm_server_destroy.argtypes = [vp]
+            L.phmm_server_destroy.restype = None
+            L.phmm_server_submit.argtypes = [vp] + [u8p] * 5 + [u64p, ctypes.c_uint32, u8p, u64p,
+                                                               ctypes.c_uint32,
+                                                               ctypes.POINTER(ctypes.c_uint32),
+                                                               ctypes.c_uint64,
+                                                               ctypes.POINTER(ctypes.c_uint64)]
+            for f in (L.phmm_server_wait, L.phmm_server_poll):
+                f.argtypes = [vp, ctypes.c_uint64, dp, u8p, ctypes.POINTER(_RequestInfo)]
+            L.phmm_server_stats.argtypes = [vp, ctypes.POINTER(_ServerCounters)]
             _lib = L
     return _lib
 
@@ -302,6 +338,80 @@ def phmm_vector_peak(device: int = 0) -> tuple[float, float]:
     a, b = ctypes.c_double(0.0), ctypes.c_double(0.0)
     _check(lib().phmm_vector_peak(device, ctypes.byref(a), ctypes.byref(b)))
     return a.value, b.value
+
+
+class Server:
+    """A phmm_server: continuous batching of submitted regions (the C
+    runtime's worker threads do the batching; this class marshals)."""
+
+    def __init__(self, device: int = 0, precision: int = PHMM_FP32_RERUN, lanes: int | None = None,
+                 long_lanes: int | None = None, hbm_budget_bytes: int | None = None,
+                 max_batch_regions: int | None = None, short_cu_percent: int | None = None):
+        L = lib()
+        o = _ServerOptions()
+        L.phmm_server_default_options(ctypes.byref(o))
+        o.precision = precision
+        for k, v in (("lanes", lanes), ("long_lanes", long_lanes),
+                     ("hbm_budget_bytes", hbm_budget_bytes),
+                     ("max_batch_regions", max_batch_regions),
+                     ("short_cu_percent", short_cu_percent)):
+            if v is not None:
+                setattr(o, k, v)
+        h = ctypes.c_void_p()
+        _check(L.phmm_server_create(ctypes.byref(h), device, ctypes.byref(o)))
+        self._h = h
+        self._np = {}
+
+    def submit(self, region) -> int:
+        """Submit one region (a batch dict); returns its ticket."""
+        keep, args = _batch_args(region)
+        t = ctypes.c_uint64(0)
+        _check(lib().phmm_server_submit(self._h, *args, ctypes.byref(t)))
+        self._np[t.value] = args[-1]
+        return t.value
+
+    def _collect(self, fn, ticket):
+        n = self._np[ticket]
+        out = np.empty(n, np.float64)
+        flags = np.empty(n, np.uint8)
+        info = _RequestInfo()
+        rc = fn(self._h, ticket, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                flags.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), ctypes.byref(info))
+        if rc == PHMM_PENDING:
+            return None
+        del self._np[ticket]
+        _check(rc)
+        return out, flags, {n_: getattr(info, n_) for n_, _ in _RequestInfo._fields_}
+
+    def wait(self, ticket: int):
+        """Block until the region is done -> (log10 L, flags, info dict)."""
+        return self._collect(lib().phmm_server_wait, ticket)
+
+    def poll(self, ticket: int):
+        """(log10 L, flags, info) if done, else None."""
+        return self._collect(lib().phmm_server_poll, ticket)
+
+    def stats(self) -> dict:
+        c = _ServerCounters()
+        _check(lib().phmm_server_stats(self._h, ctypes.byref(c)))
+        return {n: getattr(c, n) for n, _ in _ServerCounters._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().phmm_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def phmm_copy_calib(src, dst, stream=None) -> None:

@@ -18,7 +18,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libphmm.so")
-SOURCES = ["phmm_api.hip", "phmm_pack.hip", "phmm_short.hip", "phmm_long.hip", "phmm_peak.hip"]
+SOURCES = ["phmm_api.hip", "phmm_pack.hip", "phmm_short.hip", "phmm_long.hip", "phmm_peak.hip",
+           "phmm_server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -51,6 +51,14 @@ static int fail(int code, const char* fmt, ...)
             return fail(PHMM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
     } while (0)
 
+namespace phmm {
+int set_error(int code, const char* msg)
+{
+    g_err = msg;
+    return code;
+}
+}  // namespace phmm
+
 extern "C" const char* phmm_last_error(void) { return g_err.c_str(); }
 extern "C" int phmm_num_classes(void) { return kNumClasses; }
 extern "C" int phmm_class_n(int c) { return (c >= 0 && c < kNumClasses) ? class_n(c) : -1; }

@@ -145,18 +145,31 @@ __device__ __forceinline__ double emit_sel(uint32_t w, int off, double pm, doubl
 // ---------------------------------------------------------------- row recurrence
 //
 // Per-row coefficients, computed once per read row in FP64 and stored in LDS.
-// With PRE the insert row is kept pre-multiplied by the next row's T_IM
-// (I' = T_IM_{i+1} I), so the match update needs two FMAs instead of a
-// multiply and two FMAs; the insert update then uses
-// a = T_IM_{i+1} T_MI_i and b = T_IM_{i+1} T_II_i / T_IM_i (T_IM_{l+1} = 1, so
-// the last row holds I itself).  PRE needs T_IM_i > 0 on every row; without
-// it, a = T_MI_i and b = T_II_i.
+//
+// Scaled form (SC): row r keeps J_r = T_IM_{r+1} I_r and M*_r = s_r M_r with
+// s_r = T_IM_{r+2} T_MI_{r+1} (T_IM_l = 1 past the last row, s_{l-1} = 1, so
+// the last row holds M and I themselves).  Substituting into eq.2:
+//
+//   M*_r(j) = (s_r p) (T_MM_r / s_{r-1} M*_{r-1}(j-1) + J_{r-1}(j-1)
+//                      + T_DM_r T_MD_{r-1} / s_{r-1} S*_{r-1}(j-2))
+//   J_r(j)  = M*_{r-1}(j) + T_IM_{r+1} T_II_r / T_IM_r J_{r-1}(j)
+//
+// where S* is the delete prefix of the scaled row.  Both coefficients that
+// would multiply J and M* are 1, so a cell costs two FMAs and a multiply for
+// M and one FMA for I.  The scale factors are per row, not cumulative; the
+// form needs T_IM_r > 0 and s_r bounded away from 0 (checked per pack, see
+// sc_ok).  Otherwise the plain form runs: a = T_MI_r, b = T_II_r, unscaled.
 template <typename R>
 struct RowRec {
     R pm, px, tmm, cd, a, b, tim, pad;
 };
 
-template <typename R, bool PRE>
+// Largest insertion Phred byte of the scaled form: keeps s_r >= 2^-24 for
+// every gap byte >= 1 (T_IM >= 1 - 10^-0.1), so the scaled rows stay within
+// 24 binary orders of the plain ones.
+constexpr int kScMaxInsQ = 65;
+
+template <typename R, bool SC>
 __device__ __forceinline__ RowRec<R> make_row_rec(const Batch& B, const double* p64, uint64_t a,
                                                   int i, int l)
 {
@@ -168,16 +181,24 @@ __device__ __forceinline__ RowRec<R> make_row_rec(const Batch& B, const double* 
     double tmm = 1.0 - (tmi + tmd);
     tmm = tmm < 0.0 ? 0.0 : tmm;
     const double pm = 1.0 - eps, px = eps / 3.0, tim = 1.0 - g;
+    const double cd = tim * tmd_prev;  // T_DM_i T_MD_{i-1}
     RowRec<R> r;
-    r.pm = (R)pm;
-    r.px = (R)px;
-    r.tmm = (R)tmm;
-    r.cd = (R)(tim * tmd_prev);  // T_DM_i T_MD_{i-1}
-    if (PRE) {
-        const double tim_next = i + 1 < l ? 1.0 - p64[B.gq[a + 1]] : 1.0;
-        r.a = (R)(tim_next * tmi);
-        r.b = (R)(tim_next * g / tim);
+    if (SC) {
+        const double tim1 = i + 1 < l ? 1.0 - p64[B.gq[a + 1]] : 1.0;  // T_IM_{i+1}
+        const double tim2 = i + 2 < l ? 1.0 - p64[B.gq[a + 2]] : 1.0;  // T_IM_{i+2}
+        const double s = i + 1 < l ? tim2 * p64[B.iq[a + 1]] : 1.0;    // s_i
+        const double sp = tim1 * tmi;                                   // s_{i-1}
+        r.pm = (R)(s * pm);
+        r.px = (R)(s * px);
+        r.tmm = (R)(tmm / sp);
+        r.cd = (R)(cd / sp);
+        r.a = (R)1;
+        r.b = (R)(tim1 * g / tim);
     } else {
+        r.pm = (R)pm;
+        r.px = (R)px;
+        r.tmm = (R)tmm;
+        r.cd = (R)cd;
         r.a = (R)tmi;
         r.b = (R)g;
     }
@@ -186,7 +207,8 @@ __device__ __forceinline__ RowRec<R> make_row_rec(const Batch& B, const double* 
     return r;
 }
 
-// Row 1: M(1,j) = P(r_1|h_j) T_DM_1 C0/k, I(1,j) = 0.
+// Row 1: M(1,j) = P(r_1|h_j) T_DM_1 C0/k (times s_0 in the scaled form, which
+// the record's pm and px carry), I(1,j) = 0.
 template <typename R, int N>
 __device__ __forceinline__ void row_first(R (&Mo)[N], R (&Io)[N], const uint32_t (&hc)[(N + 3) / 4],
                                           int bidx, const RowRec<R>& c, R minit, R g, R& Vp)
@@ -207,7 +229,7 @@ __device__ __forceinline__ void row_first(R (&Mo)[N], R (&Io)[N], const uint32_t
 // Rows 2..l of the row-level recurrence: reads row i-1 from (Mi, Ii) and
 // writes row i to (Mo, Io).  T rebuilds S(i-1, .) from the lane's carry C, V
 // accumulates the new row's window sum for the next scan.
-template <typename R, int N, bool PRE>
+template <typename R, int N, bool SC>
 __device__ __forceinline__ void row_step(const R (&Mi)[N], const R (&Ii)[N], R (&Mo)[N], R (&Io)[N],
                                          const uint32_t (&hc)[(N + 3) / 4], int bidx,
                                          const RowRec<R>& c, R Mleft, R Ileft, R C, R gprev,
@@ -219,11 +241,11 @@ __device__ __forceinline__ void row_step(const R (&Mi)[N], const R (&Ii)[N], R (
         const R mprev = n == 0 ? Mleft : Mi[n - 1];
         const R iprev = n == 0 ? Ileft : Ii[n - 1];
         const R p = emit_sel(hc[n / 4], 8 * (n % 4) + bidx, c.pm, c.px);
-        const R x = PRE ? fmaR(c.cd, T, fmaR(c.tmm, mprev, iprev))
-                        : fmaR(c.cd, T, fmaR(c.tim, iprev, c.tmm * mprev));
+        const R x = SC ? fmaR(c.cd, T, fmaR(c.tmm, mprev, iprev))
+                       : fmaR(c.cd, T, fmaR(c.tim, iprev, c.tmm * mprev));
         const R m = p * x;
         Mo[n] = m;
-        Io[n] = fmaR(c.b, Ii[n], c.a * Mi[n]);
+        Io[n] = SC ? fmaR(c.b, Ii[n], Mi[n]) : fmaR(c.b, Ii[n], c.a * Mi[n]);
         T = fmaR(gprev, T, mprev);
         if (n < N - 1) V = fmaR(gcur, V, m);
     }

@@ -101,6 +101,9 @@ struct Work {
     uint32_t max_long_tiles;
 };
 
+// Sets the calling thread's phmm_last_error() message; returns code.
+int set_error(int code, const char* msg);
+
 struct Policy {
     int precision;          // 0 FP32+rerun, 1 FP64 plain
     int force_class;        // -1 or class index

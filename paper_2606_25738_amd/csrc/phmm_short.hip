@@ -161,12 +161,15 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
         const uint64_t roff = b.read_off[r];
         const int l = (int)(b.read_off[r + 1] - roff);
         const int g0 = b.gq[roff];
-        bool varying = false, tim_zero = false;
+        // scaled form possible: T_IM > 0 (gap byte >= 1) and bounded insertion
+        // bytes on every row
+        bool varying = false, sc_ok = true;
         for (int i0 = 0; i0 < l; i0 += kWave) {
             const int i = i0 + lane;
             const int gc = i < l ? (int)b.gq[roff + i] : g0;
+            const int ic = i < l ? (int)b.iq[roff + i] : 0;
             varying = varying || __ballot(gc != g0) != 0ull;
-            tim_zero = tim_zero || __ballot(gc == 0) != 0ull;  // g = 1: T_IM = 0
+            sc_ok = sc_ok && __ballot(gc == 0 || ic > kScMaxInsQ) == 0ull;
         }
         const R notstart = (lane != segstart) ? (R)1 : (R)0;
         const R minit = real ? (R)(ldexp(1.0, ScaleOf<R>::exp) / (double)k) : (R)0;
@@ -179,9 +182,9 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
         for (int n = 0; n < N; ++n) { Ma[n] = (R)0; Ia[n] = (R)0; }
         R Mleft = (R)0, Ileft = (R)0, C = (R)0;
 
-        // all rows of the pack; PRE selects the pre-scaled insert row
-        auto run_rows = [&](auto pre_tag) {
-            constexpr bool PRE = decltype(pre_tag)::value;
+        // all rows of the pack; SC selects the scaled form of the rows
+        auto run_rows = [&](auto sc_tag) {
+            constexpr bool SC = decltype(sc_tag)::value;
             // one row of the recurrence plus the carries for the next row;
             // rows alternate between the (Ma, Ia) and (Mb, Ib) register sets
             auto do_row = [&](int tt, bool first, const R(&Mi)[N], const R(&Ii)[N], R(&Mo)[N],
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
                 if (first)
                     row_first<R, N>(Mo, Io, hc, bidx, c, minit, gcur, Vp);
                 else
-                    row_step<R, N, PRE>(Mi, Ii, Mo, Io, hc, bidx, c, Mleft, Ileft, C, gprev,
+                    row_step<R, N, SC>(Mi, Ii, Mo, Io, hc, bidx, c, Mleft, Ileft, C, gprev,
                                         gcur, Vp);
                 // carries for the next row: left neighbour's last column, and
                 // the exclusive scan of the shifted window sums
@@ -216,7 +219,7 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
                     const int i = i0 + lane;
                     if (i < l) {
                         const uint64_t a = roff + (uint64_t)i;
-                        rec[lane] = make_row_rec<R, PRE>(b, t.p64, a, i, l);
+                        rec[lane] = make_row_rec<R, SC>(b, t.p64, a, i, l);
                         rinfo[lane] = read_base_index(b.reads[a]) | ((int)b.gq[a] << 16);
                     }
                 }
@@ -234,10 +237,10 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
                 }
             }
         };
-        if (tim_zero)
-            run_rows(std::false_type{});
-        else
+        if (sc_ok)
             run_rows(std::true_type{});
+        else
+            run_rows(std::false_type{});
 
         // ---- eq.4: S = sum_j M(l,j) + I(l,j) over the real columns
         R s = (R)0;

@@ -26,6 +26,8 @@ them with the published shapes only):
   cfg2  96 long pairs: 32 each of 10k, 32k and 100k bp, haplotype 1.1x read
   cfg3  genome-scale: regions of 150 bp reads, 2-16 variant haplotypes of
         150-600 bp, lognormal read counts, qualities Phred 2-41
+  cfg4  served stream: cfg3 regions, 5% of them long-read regions (reads of
+        1k-20k bp, 2-4 haplotypes of 1.1x read length)
 """
 from __future__ import annotations
 
@@ -63,6 +65,9 @@ class _Cfg(ctypes.Structure):
         ("q_lo", ctypes.c_int), ("q_hi", ctypes.c_int),
         ("ins_q", ctypes.c_int), ("del_q", ctypes.c_int), ("gcp_q", ctypes.c_int),
         ("offset_mode", ctypes.c_int), ("offset_frac", ctypes.c_double),
+        ("long_frac", ctypes.c_double), ("long_len_lo", ctypes.c_int),
+        ("long_len_hi", ctypes.c_int), ("long_haps_lo", ctypes.c_int),
+        ("long_haps_hi", ctypes.c_int), ("long_hap_factor", ctypes.c_double),
     ]
 
 
@@ -80,7 +85,9 @@ _BASE = dict(n_haps_lo=8, n_haps_hi=8, hap_len_lo=200, hap_len_hi=200, hap_mode=
              reads_cap=400, read_len_lo=100, read_len_hi=100, n_len_classes=0,
              len_classes=(0, 0, 0, 0), regions_per_class=1, hap_len_factor=0.0,
              p_sub=0.01, p_indel=0.001, indel_lo=1, indel_hi=3, q_lo=10, q_hi=40,
-             ins_q=45, del_q=45, gcp_q=10, offset_mode=0, offset_frac=0.0)
+             ins_q=45, del_q=45, gcp_q=10, offset_mode=0, offset_frac=0.0,
+             long_frac=0.0, long_len_lo=0, long_len_hi=0, long_haps_lo=0, long_haps_hi=0,
+             long_hap_factor=0.0)
 
 CONFIGS = {
     # one region, plain FP64 (8 i.i.d. haps x 200 bp, 64 reads x 100 bp)
@@ -98,6 +105,13 @@ CONFIGS = {
                  hap_len_hi=600, hap_mode=1, reads_mode=1, read_len_lo=150, read_len_hi=150,
                  p_sub=0.005, p_indel=0.0005, q_lo=2, q_hi=41),
 }
+# served request stream: regions as in the genome-scale workload, 5% of them
+# long (all reads of one length U{1000..20000}, 2-4 haplotypes of 1.1x that
+# length, same error and quality model); the region count is a pool the
+# arrival process draws from in order
+CONFIGS["cfg4"] = dict(CONFIGS["cfg3"], regions=1000000, seed=4, long_frac=0.05,
+                       long_len_lo=1000, long_len_hi=20000, long_haps_lo=2, long_haps_hi=4,
+                       long_hap_factor=1.1)
 
 _lock = threading.Lock()
 _lib = None
@@ -220,4 +234,21 @@ def subset_pairs(batch: dict, pair_idx) -> dict:
     """Same inputs, restricted pair list."""
     out = dict(batch)
     out["pair_list"] = np.ascontiguousarray(batch["pair_list"][np.asarray(pair_idx)])
+    return out
+
+
+def region_slice(batch: dict, i: int) -> dict:
+    """Region i of a generated batch as a batch of its own (local offsets)."""
+    rp, rr, rh = batch["region_pairs"], batch["region_reads"], batch["region_haps"]
+    r0, r1 = int(rr[i]), int(rr[i + 1])
+    h0, h1 = int(rh[i]), int(rh[i + 1])
+    ro = batch["read_offsets"][r0:r1 + 1]
+    ho = batch["hap_offsets"][h0:h1 + 1]
+    b0, b1 = int(ro[0]), int(ro[-1])
+    out = {k: batch[k][b0:b1] for k in ("reads", "base_quals", "ins_quals", "del_quals", "gcp")}
+    out["read_offsets"] = (ro - ro[0]).astype(np.uint64)
+    out["haplotypes"] = batch["haplotypes"][int(ho[0]):int(ho[-1])]
+    out["hap_offsets"] = (ho - ho[0]).astype(np.uint64)
+    pl = batch["pair_list"][int(rp[i]):int(rp[i + 1])].astype(np.int64)
+    out["pair_list"] = np.stack([pl[:, 0] - r0, pl[:, 1] - h0], axis=1).astype(np.uint32)
     return out

@@ -36,6 +36,13 @@ typedef struct {
     int q_lo, q_hi, ins_q, del_q, gcp_q;
     int offset_mode;               /* 0: U{0..k-l}; 1: U{0..floor(frac*l)}        */
     double offset_frac;
+    /* Mixed streams: a region is "long" with probability long_frac; all its
+     * reads then have one length ~ U{long_len_lo..hi}, it has
+     * U{long_haps_lo..hi} haplotypes of length round(long_hap_factor * len). */
+    double long_frac;
+    int long_len_lo, long_len_hi;
+    int long_haps_lo, long_haps_hi;
+    double long_hap_factor;
 } synth_cfg;
 
 typedef struct {
@@ -114,10 +121,14 @@ static int gen_region(const synth_cfg* c, uint64_t seed, uint64_t region,
 {
     rng_t r = rng_for(seed, region);
     int fill = o != NULL;
-    int H = next_int(&r, c->n_haps_lo, c->n_haps_hi);
+    int is_long = c->long_frac > 0 && next_unit(&r) < c->long_frac;
+    int H = is_long ? next_int(&r, c->long_haps_lo, c->long_haps_hi)
+                    : next_int(&r, c->n_haps_lo, c->n_haps_hi);
     /* Read length is drawn up front when the haplotype length depends on it. */
-    int first_len = region_read_len(c, &r, region);
-    int K = c->hap_len_factor > 0 ? (int)llround(c->hap_len_factor * first_len)
+    int first_len = is_long ? next_int(&r, c->long_len_lo, c->long_len_hi)
+                            : region_read_len(c, &r, region);
+    int K = is_long ? (int)llround(c->long_hap_factor * first_len)
+          : c->hap_len_factor > 0 ? (int)llround(c->hap_len_factor * first_len)
                                   : next_int(&r, c->hap_len_lo, c->hap_len_hi);
     int maxlen = K + c->var_hi * (c->var_indel_hi > 0 ? c->var_indel_hi : 0) + 8;
     uint8_t* hbuf = (uint8_t*)malloc((size_t)maxlen * (size_t)(H > 0 ? H : 1));
@@ -175,7 +186,7 @@ static int gen_region(const synth_cfg* c, uint64_t seed, uint64_t region,
     }
     uint64_t read_bases = 0;
     for (int q = 0; q < R; ++q) {
-        int l = q == 0 ? first_len : region_read_len(c, &r, region);
+        int l = (q == 0 || is_long) ? first_len : region_read_len(c, &r, region);
         int src = next_int(&r, 0, H - 1);
         int k = hlen[src];
         const uint8_t* hs = hbuf + (size_t)src * maxlen;

@@ -152,3 +152,14 @@ def test_no_device_fails_loudly():
     with pytest.raises(phmm.PhmmError) as e:
         phmm.Context()
     assert e.value.code == phmm.PHMM_EDEVICE
+    with pytest.raises(phmm.PhmmError) as e:
+        phmm.Server()
+    assert e.value.code == phmm.PHMM_EDEVICE
+
+
+def test_server_rejects_bad_options():
+    for kw in (dict(lanes=0), dict(lanes=2, long_lanes=2), dict(hbm_budget_bytes=1 << 20),
+               dict(short_cu_percent=101), dict(precision=7)):
+        with pytest.raises(phmm.PhmmError) as e:
+            phmm.Server(**kw)
+        assert e.value.code == phmm.PHMM_EINVAL, kw

@@ -193,6 +193,36 @@ def test_edge_cases(ctx32, ctx64):
         check(b, out, fl, plain64=plain)
 
 
+def test_scaled_row_form_limits(ctx32, ctx64):
+    """Rows run in a scaled form when every insertion byte is <= 65 and every
+    gap byte >= 1, and in the plain form otherwise; both sides of that limit,
+    with the smallest row scale (insertion 65, gap 1) and extreme base
+    qualities, match the oracle."""
+    rng = np.random.default_rng(12)
+    src = rnd(rng, 2000)
+    rd = bytearray(src[200:350])
+    for j in rng.integers(0, 150, 4):
+        rd[j] = ord("ACGT"[int(rng.integers(0, 4))])
+    rd = bytes(rd)
+    hap = src[150:150 + 420]
+    bq_ext = np.where(np.arange(150) % 7 == 0, 255, rng.integers(2, 60, 150))
+    pairs = [
+        (rd, hap, rng.integers(2, 41, 150), 65, 45, 1),                       # scaled, smallest s
+        (rd, hap, rng.integers(2, 41, 150), 66, 45, 1),                       # plain
+        (rd, hap, bq_ext, 65, 45, 1),                                          # tiny p_mis x s
+        (rd, hap, rng.integers(2, 41, 150), rng.integers(0, 66, 150), rng.integers(10, 60, 150),
+         rng.integers(1, 41, 150)),                                            # scaled, varying
+        (rd, hap, rng.integers(2, 41, 150), rng.integers(0, 66, 150), 45,
+         np.where(np.arange(150) == 77, 0, 10)),                               # one gap byte 0
+        (rd[:1], hap[:40], 20, 65, 45, 1),                                     # one-row read
+        (rd[:2], hap[:40], 20, 65, 45, 1),                                     # two-row read
+    ]
+    b = make_batch(pairs)
+    for c, plain in ((ctx64, True), (ctx32, False)):
+        out, fl = phmm.phmm_forward_batch(c, b)
+        check(b, out, fl, plain64=plain)
+
+
 def test_unsorted_pairs_and_duplicates(ctx32):
     b = synth.generate("cfg1", 11, 3)
     pl = b["pair_list"]
@@ -274,3 +304,15 @@ def test_vector_peak_calibration():
     fp32, fp64 = phmm.phmm_vector_peak(0)
     say("vector FMA peak: FP32 %.1f, FP64 %.1f TFLOP/s" % (fp32, fp64))
     assert 10 < fp64 < 200 and 10 < fp32 < 400
+
+
+def test_copy_calibration_kernel():
+    import torch
+    n = (1 << 20) + 48
+    src = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda:0")
+    dst = torch.zeros_like(src)
+    phmm.phmm_copy_calib(src, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    with pytest.raises(phmm.PhmmError):
+        phmm.phmm_copy_calib(src[:17], dst[:17])  # not a multiple of 16
