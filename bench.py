@@ -14,7 +14,6 @@ from __future__ import annotations
 
 import argparse
 import csv
-import glob
 import hashlib
 import json
 import math
@@ -76,10 +75,14 @@ def run_oracle(batch, idx, cores):
     return vals, wall, cpu
 
 
+# sources that decide what the FP32 short kernels and the packer do
+TRAFFIC_SOURCES = ("phmm_short.hip", "phmm_dev.h", "phmm_internal.h", "phmm_pack.hip")
+
+
 def sources_digest():
     """sha256 over the kernel sources (any change invalidates stored counters)."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(CSRC, "*"))):
+    for f in sorted(os.path.join(CSRC, n) for n in TRAFFIC_SOURCES):
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
