@@ -110,7 +110,7 @@ def summarize_traffic(fetch_csv, write_csv, out_path, regions, calib_mib, comman
         factor = calib_mib * 1024.0 / calib[-1]
         per = {}
         for r in rows:
-            m = re.search(r"short_kernel<float, (\d+)>", r["Kernel_Name"])
+            m = re.search(r"short_kernel<float, (\d+), \d+>", r["Kernel_Name"])
             if m:
                 per[int(m.group(1))] = per.get(int(m.group(1)), 0.0) + float(r["Counter_Value"])
         res[name] = dict(factor=factor, calib_kib=calib[-1], per_class=per)
@@ -120,7 +120,8 @@ def summarize_traffic(fetch_csv, write_csv, out_path, regions, calib_mib, comman
     lines = ["# HBM traffic of the FP32 short-pair kernels, genome-scale WGS-like batch", "",
              "Commands (repository root, one MI355X):", ""]
     lines += ["    " + c for c in commands]
-    lines += ["", "Workload: %d regions, one step (11 launches of `short_kernel<float, c>`)." % regions,
+    lines += ["", "Workload: %d regions, one step (22 launches of `short_kernel<float, c, kind>`: the fast"
+              " and the general FP32 kernel of each class; counts per class summed over both)." % regions,
               "Counters are KiB per dispatch. Scale factor = known bytes of the calibration copy",
               "(`copy_calib_kernel`, %d MiB read and %d MiB written) / the counter's reading for it." %
               (calib_mib, calib_mib), "",
@@ -378,10 +379,11 @@ def main():
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                 frac=round(achieved / FP32_PEAK_TFLOPS, 4),
                 traffic=None if traffic is None else round(traffic),
-                traffic_unit="bytes per step (11 launches)",
+                traffic_unit="bytes per step (22 launches)",
                 algorithmic_bytes=int(alg_bytes), hbm_gbs_from_traffic=None if traffic is None
                 else round(traffic / (ph["short_ms"] / 1e3) / 1e9, 2), copy_calib_gbs=copy_gbs,
-                kernel="FP32 short-pair kernels (11 column-class launches per step)",
+                kernel="FP32 short-pair kernels (fast and general kernel of each of the 11 column "
+                       "classes: 22 launches per step)",
                 kernel_ms=round(ph["short_ms"], 3),
                 measured_peak_fp32=round(peak32, 2), measured_peak_fp64=round(peak64, 2),
                 frac_of_measured=round(achieved / peak32, 4))

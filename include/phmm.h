@@ -220,6 +220,9 @@ typedef struct phmm_counts {
     uint64_t long_pairs;   /* pairs sent to the long-pair kernel       */
     uint64_t long_tiles;   /* wavefront tiles of the long-pair kernel  */
     uint64_t lane_columns; /* sum over packs of 64*N (occupied cells per row) */
+    uint64_t deferred_packs; /* FP32 packs run by the general FP32 kernel (a read
+                                with several gap bytes, a gap byte of 0 or an
+                                insertion byte above 65)                     */
 } phmm_counts;
 int phmm_last_counts(phmm_ctx* ctx, void* d_workspace, phmm_counts* out);
 

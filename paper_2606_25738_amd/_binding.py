@@ -56,7 +56,7 @@ class _DeviceBatch(ctypes.Structure):
 class _Counts(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("packs_fp32", "packs_fp64", "rerun_items",
                                                 "rerun_pairs", "long_pairs", "long_tiles",
-                                                "lane_columns")]
+                                                "lane_columns", "deferred_packs")]
 
 
 class _ServerOptions(ctypes.Structure):

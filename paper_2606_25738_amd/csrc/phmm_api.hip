@@ -15,13 +15,12 @@
 #include "phmm_internal.h"
 
 namespace phmm {
-void launch_short(bool fp32, int cls, int grid, hipStream_t s, const Batch& b, const Tables& t,
+void launch_short(int kind, int cls, int grid, hipStream_t s, const Batch& b, const Tables& t,
                   const Work& w, const Policy& p);
-const void* short_kernel_ptr(bool fp32, int cls);
+const void* short_kernel_ptr(int kind, int cls);
 __global__ void reset_kernel(Counters* c);
-__global__ void pack_count_kernel(Batch b, Work w, Policy pol);
-__global__ void pack_scan_kernel(Work w, uint32_t nblocks);
-__global__ void pack_emit_kernel(Batch b, Work w, Policy pol);
+void launch_pack(hipStream_t s, const Batch& b, const Work& w, const Policy& pol);
+uint32_t scan_chunks(uint32_t n_pack_blocks);
 void launch_long(hipStream_t s, int grid, const Batch& b, const Tables& t, const Work& w,
                  const Policy& p);
 const void* long_kernel_ptr();
@@ -82,7 +81,7 @@ struct phmm_ctx {
     phmm_options opt{};
     hipStream_t stream = nullptr;
     int cus = 0;
-    int grid_short[2][kNumClasses] = {};  // [fp32?0:1] persistent wavefronts per class
+    int grid_short[kNumKernelKinds][kNumClasses] = {};  // persistent wavefronts per kernel
     int grid_long = 0;
     double* d_p64 = nullptr;
     double* d_pw64 = nullptr;
@@ -186,12 +185,12 @@ static int create_impl(phmm_ctx* c, int device)
     c->cus = prop.multiProcessorCount;
     HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     for (auto& e : c->ev) HIP_TRY(hipEventCreate(&e));
-    for (int prec = 0; prec < 2; ++prec)
+    for (int kind = 0; kind < kNumKernelKinds; ++kind)
         for (int cls = 0; cls < kNumClasses; ++cls) {
             int per_cu = 0;
             HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, short_kernel_ptr(prec == 0, cls), kWave, 0));
-            c->grid_short[prec][cls] = std::max(1, per_cu) * c->cus;
+                &per_cu, short_kernel_ptr(kind, cls), kWave, 0));
+            c->grid_short[kind][cls] = std::max(1, per_cu) * c->cus;
         }
     int per_cu = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, long_kernel_ptr(), kWave, 0));
@@ -221,8 +220,8 @@ extern "C" int phmm_create(phmm_ctx** out, int device, const phmm_options* opt)
 
 // ---------------------------------------------------------------- workspace
 struct Layout {
-    size_t ctr, chunk_info, blk_cnt, blk_lc, packs, items, long_list, long_pref, ring, slot, part,
-        total;
+    size_t ctr, chunk_info, blk_cnt, blk_lc, chunk_part, packs, items, deferred, long_list,
+        long_pref, ring, slot, part, total;
 };
 
 static uint64_t pack_blocks(uint64_t n_pairs) { return (n_pairs + kPackBlock - 1) / kPackBlock; }
@@ -237,10 +236,12 @@ static Layout layout_for(const phmm_ctx* c, uint64_t n_pairs)
     const uint32_t slots = long_slots(c->grid_long);
     L.ctr = o; o = align256(o + sizeof(Counters));
     L.chunk_info = o; o = align256(o + n * 4);
-    L.blk_cnt = o; o = align256(o + pack_blocks(n) * 2 * kNumClasses * 4);
+    L.blk_cnt = o; o = align256(o + pack_blocks(n) * kSeg * 4);
     L.blk_lc = o; o = align256(o + pack_blocks(n) * 8);
+    L.chunk_part = o; o = align256(o + (size_t)scan_chunks((uint32_t)pack_blocks(n)) * kSeg * 4);
     L.packs = o; o = align256(o + n * sizeof(Pack));
     L.items = o; o = align256(o + n * sizeof(Item));
+    L.deferred = o; o = align256(o + n * 4);
     L.long_list = o; o = align256(o + n * 4);
     L.long_pref = o; o = align256(o + (n + 1) * 4);
     L.ring = o; o = align256(o + (size_t)slots * (kRing + 1) * 4 * sizeof(double));
@@ -268,8 +269,12 @@ static Work work_for(phmm_ctx* c, void* ws, uint64_t n_pairs)
     w.chunk_info = reinterpret_cast<uint32_t*>(base + L.chunk_info);
     w.blk_cnt = reinterpret_cast<uint32_t*>(base + L.blk_cnt);
     w.blk_lanecols = reinterpret_cast<unsigned long long*>(base + L.blk_lc);
+    w.chunk_part = reinterpret_cast<uint32_t*>(base + L.chunk_part);
+    w.n_pack_blocks = (uint32_t)pack_blocks(n_pairs ? n_pairs : 1);
+    w.n_scan_chunks = scan_chunks(w.n_pack_blocks);
     w.packs = reinterpret_cast<Pack*>(base + L.packs);
     w.items = reinterpret_cast<Item*>(base + L.items);
+    w.deferred = reinterpret_cast<uint32_t*>(base + L.deferred);
     w.long_list = reinterpret_cast<uint32_t*>(base + L.long_list);
     w.long_pref = reinterpret_cast<uint32_t*>(base + L.long_pref);
     w.long_ring = reinterpret_cast<double*>(base + L.ring);
@@ -292,20 +297,18 @@ static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s)
     const bool timed = c->opt.timing != 0;
     if (timed) HIP_TRY(hipEventRecord(c->ev[0], s));
     hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, s, w.ctr);
-    if (b.n_pairs > 0) {
-        const unsigned blocks = (unsigned)pack_blocks(b.n_pairs);
-        hipLaunchKernelGGL(pack_count_kernel, dim3(blocks), dim3(kPackBlock), 0, s, b, w, pol);
-        hipLaunchKernelGGL(pack_scan_kernel, dim3(1), dim3(1024), 0, s, w, (uint32_t)blocks);
-        hipLaunchKernelGGL(pack_emit_kernel, dim3(blocks), dim3(kPackBlock), 0, s, b, w, pol);
-    }
+    if (b.n_pairs > 0) launch_pack(s, b, w, pol);
     if (timed) HIP_TRY(hipEventRecord(c->ev[1], s));
     if (b.n_pairs > 0) {
-        if (pol.precision == PHMM_FP32_RERUN)
+        if (pol.precision == PHMM_FP32_RERUN) {
             for (int cls = 0; cls < kNumClasses; ++cls)
-                launch_short(true, cls, c->grid_short[0][cls], s, b, t, w, pol);
+                launch_short(kFast32, cls, c->grid_short[kFast32][cls], s, b, t, w, pol);
+            for (int cls = 0; cls < kNumClasses; ++cls)
+                launch_short(kGen32, cls, c->grid_short[kGen32][cls], s, b, t, w, pol);
+        }
         if (timed) HIP_TRY(hipEventRecord(c->ev[2], s));
         for (int cls = 0; cls < kNumClasses; ++cls)
-            launch_short(false, cls, c->grid_short[1][cls], s, b, t, w, pol);
+            launch_short(kAll64, cls, c->grid_short[kAll64][cls], s, b, t, w, pol);
         if (timed) HIP_TRY(hipEventRecord(c->ev[3], s));
         launch_long(s, c->grid_long, b, t, w, pol);
     } else if (timed) {
@@ -379,6 +382,7 @@ extern "C" int phmm_last_counts(phmm_ctx* c, void* d_ws, phmm_counts* out)
     out->long_pairs = h.n_long;
     out->long_tiles = h.long_tiles;
     out->lane_columns = h.lane_columns;
+    for (int k = 0; k < kNumClasses; ++k) out->deferred_packs += h.defer_cnt[k];
     return PHMM_OK;
 }
 

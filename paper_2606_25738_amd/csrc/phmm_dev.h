@@ -164,10 +164,9 @@ struct RowRec {
     R pm, px, tmm, cd, a, b, tim, pad;
 };
 
-// Largest insertion Phred byte of the scaled form: keeps s_r >= 2^-24 for
-// every gap byte >= 1 (T_IM >= 1 - 10^-0.1), so the scaled rows stay within
-// 24 binary orders of the plain ones.
-constexpr int kScMaxInsQ = 65;
+// kScMaxInsQ (the largest insertion Phred byte of the scaled form) keeps
+// s_r >= 2^-24 for every gap byte >= 1 (T_IM >= 1 - 10^-0.1), so the scaled
+// rows stay within 24 binary orders of the plain ones.
 
 template <typename R, bool SC>
 __device__ __forceinline__ RowRec<R> make_row_rec(const Batch& B, const double* p64, uint64_t a,

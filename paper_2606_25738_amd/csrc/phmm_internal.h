@@ -45,15 +45,24 @@ struct Item {             // FP64 rerun item: an FP32 pack and the subset of its
     uint32_t mask;        // bit s: pair pair_start + s is computed
 };
 
+// Pack segments: a pack belongs to one (precision, class) segment, [0] FP32,
+// [1] FP64.  The fast FP32 kernel runs the FP32 packs whose read has one gap
+// penalty on every row and fits the scaled row form; it defers the others to
+// the general FP32 kernel of the class.
+constexpr int kSeg = 2 * kNumClasses;
+enum KernelKind : int { kFast32 = 0, kGen32 = 1, kAll64 = 2, kNumKernelKinds = 3 };
+
+// Largest insertion Phred byte of the scaled row form (see make_row_rec).
+constexpr int kScMaxInsQ = 65;
+
 // Device counters of one call (lives at the start of the workspace).
 struct Counters {
-    uint32_t pack_cnt[2][kNumClasses];   // [0] = FP32 packs, [1] = FP64 packs
+    uint32_t pack_cnt[2][kNumClasses];   // [0] FP32 packs, [1] FP64 packs
     uint32_t pack_base[2][kNumClasses];
-    uint32_t pack_fill[2][kNumClasses];
-    uint32_t item_base[kNumClasses];
+    uint32_t item_base[kNumClasses];     // rerun items and deferred packs of class k
     uint32_t item_cnt[kNumClasses];      // rerun items queued by the FP32 kernels
-    uint32_t cursor32[kNumClasses];
-    uint32_t cursor64[kNumClasses];
+    uint32_t defer_cnt[kNumClasses];     // FP32 packs deferred to the general kernel
+    uint32_t cursor[kNumKernelKinds][kNumClasses];  // next pack or item of each kernel
     uint32_t n_long;
     uint32_t long_tiles;
     uint32_t long_cursor;
@@ -89,10 +98,14 @@ struct Tables {
 struct Work {
     Counters* ctr;
     uint32_t* chunk_info;  // per pair (chunk starts only)
-    uint32_t* blk_cnt;     // per packer block and segment: pack count, then offset
-    unsigned long long* blk_lanecols;
+    uint32_t* blk_cnt;     // [segment][packer block]: pack count, then offset
+    unsigned long long* blk_lanecols;  // per packer block
+    uint32_t* chunk_part;  // [segment][scan chunk]: pack count, then offset
+    uint32_t n_pack_blocks;
+    uint32_t n_scan_chunks;
     Pack* packs;           // pack array, segments per (precision, class)
     Item* items;           // FP64 items, segments per class
+    uint32_t* deferred;    // FP32 packs for the general kernel, segments per class
     uint32_t* long_list;   // long pair indices
     uint32_t* long_pref;   // n_long + 1 tile prefix
     double* long_ring;     // per tile: kRing x 4 doubles

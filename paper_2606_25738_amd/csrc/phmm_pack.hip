@@ -9,9 +9,12 @@
 // priors and the read base are uniform across the wavefront.  Haplotypes
 // longer than 64 * kMaxN columns go to the long-pair list.
 //
-// Three kernels, no contended global atomics: count (per-block per-segment
-// pack counts from LDS atomics), scan (segment bases and per-block offsets),
-// emit (each run writes its packs at its block's offset).
+// Five kernels, no contended global atomics: count (per-block segment pack
+// counts from LDS atomics, one greedy pass that sizes all classes at once),
+// a two-level scan of the counts (chunk sums, chunk offsets in one workgroup,
+// block offsets inside each chunk) and emit (each run writes its packs at
+// its block's offset).  Counts and offsets are laid out [segment][block], so
+// every scan pass reads and writes contiguous words.
 //
 // The paper bins pairs by length and runs a dedicated kernel instance per
 // sub-warp size (Section 3.2); here the binning key is the column class and
@@ -21,7 +24,7 @@
 
 namespace phmm {
 
-constexpr int kSeg = 2 * kNumClasses;  // (precision, class) segments
+constexpr int kScanChunk = 2048;  // packer blocks per scan chunk (8 per thread)
 
 __global__ void reset_kernel(Counters* c)
 {
@@ -33,35 +36,6 @@ __global__ void reset_kernel(Counters* c)
 __device__ __forceinline__ uint32_t hap_len(const Batch& b, uint32_t h)
 {
     return (uint32_t)(b.hap_off[h + 1] - b.hap_off[h]);
-}
-
-// Walks the short pairs of run [p0, p1) at class c exactly as the emitter
-// does and returns the number of packs (0 and fits = false if a pair does
-// not fit the class).  A long pair closes the current pack.
-__device__ uint32_t count_packs(const Batch& b, uint64_t p0, uint64_t p1, int c, int one_per_wave,
-                                bool* fits)
-{
-    const uint32_t N = (uint32_t)class_n(c);
-    uint32_t packs = 0, used = kWave, np = 0;
-    *fits = true;
-    for (uint64_t p = p0; p < p1; ++p) {
-        const uint32_t k = hap_len(b, b.pairs[2 * p + 1]);
-        if (k > kShortMaxCols) {
-            used = kWave;
-            np = 0;
-            continue;
-        }
-        const uint32_t s = (k + N - 1) / N;
-        if (s > (uint32_t)kWave) { *fits = false; return 0; }
-        if (one_per_wave || used + s > (uint32_t)kWave || np == (uint32_t)kMaxPairsPerPack) {
-            ++packs;
-            used = 0;
-            np = 0;
-        }
-        used += s;
-        ++np;
-    }
-    return packs;
 }
 
 __device__ __forceinline__ bool run_start(const Batch& b, uint64_t p)
@@ -77,13 +51,31 @@ __device__ __forceinline__ uint64_t run_end(const Batch& b, uint64_t p)
     return e;
 }
 
-// Pass 1: class choice and pack counts per run; long pairs to the long list.
+// Greedy packing state of one class: lanes used in the open pack, pairs in
+// it, packs so far.  A long pair closes the open pack.
+struct Greedy {
+    uint32_t used, np, packs;
+    __device__ void reset() { used = kWave; np = 0; packs = 0; }
+    __device__ void add(uint32_t s, int one_per_wave)
+    {
+        if (one_per_wave || used + s > (uint32_t)kWave || np == (uint32_t)kMaxPairsPerPack) {
+            ++packs;
+            used = 0;
+            np = 0;
+        }
+        used += s;
+        ++np;
+    }
+};
+
+// Pass 1: precision and class per run, pack counts per (segment, block);
+// long pairs to the long list.
 __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w, Policy pol)
 {
     __shared__ uint32_t cnt[kSeg];
     __shared__ unsigned long long lanecols;
     const int t = (int)threadIdx.x;
-    if (t < kSeg) cnt[t] = 0u;
+    for (int q = t; q < kSeg; q += kPackBlock) cnt[q] = 0u;
     if (t == 0) lanecols = 0ull;
     __syncthreads();
     const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + t;
@@ -92,85 +84,150 @@ __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w,
         const uint32_t r = b.pairs[2 * p];
         const uint32_t l = (uint32_t)(b.read_off[r + 1] - b.read_off[r]);
         const int prec = (pol.precision == 1 || l > pol.fp32_max_rows) ? 1 : 0;
+        Greedy g[kNumClasses];
+        bool fits[kNumClasses];
+#pragma unroll
+        for (int c = 0; c < kNumClasses; ++c) {
+            g[c].reset();
+            fits[c] = true;
+        }
         uint32_t nshort = 0;
         for (uint64_t q = p; q < e; ++q) {
-            if (hap_len(b, b.pairs[2 * q + 1]) > kShortMaxCols) {
+            const uint32_t k = hap_len(b, b.pairs[2 * q + 1]);
+            if (k > kShortMaxCols) {
                 const uint32_t idx = atomicAdd(&w.ctr->n_long, 1u);
                 w.long_list[idx] = (uint32_t)q;
-            } else {
-                ++nshort;
+#pragma unroll
+                for (int c = 0; c < kNumClasses; ++c) {
+                    g[c].used = kWave;
+                    g[c].np = 0;
+                }
+                continue;
+            }
+            ++nshort;
+#pragma unroll
+            for (int c = 0; c < kNumClasses; ++c) {
+                const uint32_t s = (k + class_n(c) - 1) / class_n(c);
+                if (s > (uint32_t)kWave) fits[c] = false;
+                else g[c].add(s, pol.one_pair_per_wave);
             }
         }
         uint32_t info = 0xffffffffu;
         if (nshort > 0) {
             int best = -1;
             float best_cost = 0.f;
-            uint32_t best_packs = 0;
+#pragma unroll
             for (int c = 0; c < kNumClasses; ++c) {
-                if (pol.force_class >= 0 && c != pol.force_class) continue;
-                bool fits;
-                const uint32_t np = count_packs(b, p, e, c, pol.one_pair_per_wave, &fits);
-                if (!fits) continue;
-                const float cost = (float)np * pol.cost[prec][c];
+                if ((pol.force_class >= 0 && c != pol.force_class) || !fits[c]) continue;
+                const float cost = (float)g[c].packs * pol.cost[prec][c];
                 if (best < 0 || cost < best_cost) {
                     best = c;
                     best_cost = cost;
-                    best_packs = np;
                 }
             }
-            if (best < 0) {  // forced class too narrow for this run: use the widest
-                bool fits;
-                best = kNumClasses - 1;
-                best_packs = count_packs(b, p, e, best, pol.one_pair_per_wave, &fits);
-            }
-            info = (uint32_t)best | ((uint32_t)prec << 4) | (best_packs << 8);
-            atomicAdd(&cnt[prec * kNumClasses + best], best_packs);
-            atomicAdd(&lanecols, (unsigned long long)best_packs * kWave * class_n(best));
+            if (best < 0) best = kNumClasses - 1;  // forced class too narrow: the widest
+            uint32_t packs = 0;
+#pragma unroll
+            for (int c = 0; c < kNumClasses; ++c)
+                if (c == best) packs = g[c].packs;
+            info = (uint32_t)best | ((uint32_t)prec << 4) | (packs << 8);
+            atomicAdd(&cnt[prec * kNumClasses + best], packs);
+            atomicAdd(&lanecols, (unsigned long long)packs * kWave * class_n(best));
         }
         w.chunk_info[p] = info;
     }
     __syncthreads();
-    if (t < kSeg) w.blk_cnt[(size_t)blockIdx.x * kSeg + t] = cnt[t];
+    for (int q = t; q < kSeg; q += kPackBlock)
+        w.blk_cnt[(size_t)q * w.n_pack_blocks + blockIdx.x] = cnt[q];
     if (t == 0) w.blk_lanecols[blockIdx.x] = lanecols;
 }
 
-// Pass 2 (one workgroup): per-segment exclusive scan over the blocks, the
-// segment bases of the pack array and the capacity of the rerun item lists.
-__global__ __launch_bounds__(1024) void pack_scan_kernel(Work w, uint32_t nblocks)
+// Block-wide exclusive scan of 256 threads x 8 values (LDS).
+__device__ void chunk_scan(uint32_t (&v)[8], uint32_t* lds, uint32_t* total)
+{
+    const int t = (int)threadIdx.x;
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint32_t x = v[j];
+        v[j] = s;
+        s += x;
+    }
+    lds[t] = s;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        const uint32_t y = t >= d ? lds[t - d] : 0u;
+        __syncthreads();
+        lds[t] += y;
+        __syncthreads();
+    }
+    const uint32_t excl = lds[t] - s;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] += excl;
+    *total = lds[255];
+    __syncthreads();
+}
+
+// Pass 2a: per (segment, chunk) sums of the block counts; lane columns.
+__global__ __launch_bounds__(256) void pack_chunk_sum_kernel(Work w)
+{
+    __shared__ uint32_t lds[256];
+    __shared__ unsigned long long lc[256];
+    const uint32_t chunk = blockIdx.x, seg = blockIdx.y;
+    const uint32_t b0 = chunk * kScanChunk + threadIdx.x * 8;
+    uint32_t v[8];
+    unsigned long long l = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint32_t q = b0 + j;
+        v[j] = q < w.n_pack_blocks ? w.blk_cnt[(size_t)seg * w.n_pack_blocks + q] : 0u;
+        if (seg == 0 && q < w.n_pack_blocks) l += w.blk_lanecols[q];
+    }
+    uint32_t total;
+    chunk_scan(v, lds, &total);
+    if (threadIdx.x == 0) w.chunk_part[(size_t)seg * w.n_scan_chunks + chunk] = total;
+    if (seg == 0) {
+        lc[threadIdx.x] = l;
+        __syncthreads();
+        for (int d = 128; d > 0; d >>= 1) {
+            if ((int)threadIdx.x < d) lc[threadIdx.x] += lc[threadIdx.x + d];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) atomicAdd(&w.ctr->lane_columns, lc[0]);
+    }
+}
+
+// Pass 2b (one workgroup): chunk offsets per segment, segment bases of the
+// pack array and the capacity of the rerun item lists.
+__global__ __launch_bounds__(1024) void pack_scan_kernel(Work w)
 {
     __shared__ uint32_t part[1024];
     __shared__ uint32_t seg_total[kSeg];
-    __shared__ unsigned long long lc[1024];
     const int t = (int)threadIdx.x;
-    const uint32_t per = (nblocks + 1023u) / 1024u;
-    const uint32_t lo = (uint32_t)t * per, hi = lo + per < nblocks ? lo + per : nblocks;
+    const uint32_t n = w.n_scan_chunks;
+    const uint32_t per = (n + 1023u) / 1024u;
+    const uint32_t lo = (uint32_t)t * per, hi = lo + per < n ? lo + per : n;
     for (int s = 0; s < kSeg; ++s) {
+        uint32_t* cp = w.chunk_part + (size_t)s * n;
         uint32_t sum = 0;
-        for (uint32_t q = lo; q < hi; ++q) sum += w.blk_cnt[(size_t)q * kSeg + s];
+        for (uint32_t q = lo; q < hi; ++q) sum += cp[q];
         part[t] = sum;
         __syncthreads();
-        if (t == 0) {
-            uint32_t acc = 0;
-            for (int q = 0; q < 1024; ++q) {
-                const uint32_t v = part[q];
-                part[q] = acc;
-                acc += v;
-            }
-            seg_total[s] = acc;
+        for (int d = 1; d < 1024; d <<= 1) {
+            const uint32_t y = t >= d ? part[t - d] : 0u;
+            __syncthreads();
+            part[t] += y;
+            __syncthreads();
         }
-        __syncthreads();
-        uint32_t acc = part[t];
+        uint32_t acc = part[t] - sum;
         for (uint32_t q = lo; q < hi; ++q) {
-            const uint32_t v = w.blk_cnt[(size_t)q * kSeg + s];
-            w.blk_cnt[(size_t)q * kSeg + s] = acc;  // becomes the block's offset in the segment
+            const uint32_t v = cp[q];
+            cp[q] = acc;  // becomes the chunk's offset in the segment
             acc += v;
         }
+        if (t == 1023) seg_total[s] = part[1023];
         __syncthreads();
     }
-    unsigned long long sum = 0;
-    for (uint32_t q = lo; q < hi; ++q) sum += w.blk_lanecols[q];
-    lc[t] = sum;
-    __syncthreads();
     if (t == 0) {
         Counters* c = w.ctr;
         uint32_t acc = 0;
@@ -182,16 +239,29 @@ __global__ __launch_bounds__(1024) void pack_scan_kernel(Work w, uint32_t nblock
             }
         uint32_t acc2 = 0;
         for (int k = 0; k < kNumClasses; ++k) {
-            c->item_base[k] = acc2;  // reruns of class k: at most one item per FP32 pack
+            // class k: at most one rerun item, or one deferral, per FP32 pack
+            c->item_base[k] = acc2;
             acc2 += c->pack_cnt[0][k];
-            c->item_cnt[k] = 0;
-            c->cursor32[k] = 0;
-            c->cursor64[k] = 0;
         }
-        unsigned long long tot = 0;
-        for (int q = 0; q < 1024; ++q) tot += lc[q];
-        c->lane_columns = tot;
     }
+}
+
+// Pass 2c: block offsets = chunk offset + exclusive scan inside the chunk.
+__global__ __launch_bounds__(256) void pack_block_offset_kernel(Work w)
+{
+    __shared__ uint32_t lds[256];
+    const uint32_t chunk = blockIdx.x, seg = blockIdx.y;
+    const uint32_t b0 = chunk * kScanChunk + threadIdx.x * 8;
+    uint32_t* bc = w.blk_cnt + (size_t)seg * w.n_pack_blocks;
+    uint32_t v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = b0 + j < w.n_pack_blocks ? bc[b0 + j] : 0u;
+    uint32_t total;
+    chunk_scan(v, lds, &total);
+    const uint32_t base = w.chunk_part[(size_t)seg * w.n_scan_chunks + chunk];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (b0 + j < w.n_pack_blocks) bc[b0 + j] = base + v[j];
 }
 
 // Pass 3: write the packs at the block's offset in each segment.
@@ -199,7 +269,7 @@ __global__ __launch_bounds__(kPackBlock) void pack_emit_kernel(Batch b, Work w, 
 {
     __shared__ uint32_t fill[kSeg];
     const int t = (int)threadIdx.x;
-    if (t < kSeg) fill[t] = 0u;
+    for (int q = t; q < kSeg; q += kPackBlock) fill[q] = 0u;
     __syncthreads();
     const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + t;
     if (p >= b.n_pairs || !run_start(b, p)) return;
@@ -208,7 +278,8 @@ __global__ __launch_bounds__(kPackBlock) void pack_emit_kernel(Batch b, Work w, 
     const int c = (int)(info & 15u), prec = (int)((info >> 4) & 1u);
     const uint32_t npk = info >> 8;
     const int s = prec * kNumClasses + c;
-    const uint32_t slot = w.ctr->pack_base[prec][c] + w.blk_cnt[(size_t)blockIdx.x * kSeg + s] +
+    const uint32_t slot = w.ctr->pack_base[prec][c] +
+                          w.blk_cnt[(size_t)s * w.n_pack_blocks + blockIdx.x] +
                           atomicAdd(&fill[s], npk);
     const uint64_t e = run_end(b, p);
     const uint32_t N = (uint32_t)class_n(c);
@@ -241,5 +312,16 @@ __global__ __launch_bounds__(kPackBlock) void pack_emit_kernel(Batch b, Work w, 
     }
     flush();
 }
+
+void launch_pack(hipStream_t s, const Batch& b, const Work& w, const Policy& pol)
+{
+    hipLaunchKernelGGL(pack_count_kernel, dim3(w.n_pack_blocks), dim3(kPackBlock), 0, s, b, w, pol);
+    hipLaunchKernelGGL(pack_chunk_sum_kernel, dim3(w.n_scan_chunks, kSeg), dim3(256), 0, s, w);
+    hipLaunchKernelGGL(pack_scan_kernel, dim3(1), dim3(1024), 0, s, w);
+    hipLaunchKernelGGL(pack_block_offset_kernel, dim3(w.n_scan_chunks, kSeg), dim3(256), 0, s, w);
+    hipLaunchKernelGGL(pack_emit_kernel, dim3(w.n_pack_blocks), dim3(kPackBlock), 0, s, b, w, pol);
+}
+
+uint32_t scan_chunks(uint32_t n_pack_blocks) { return (n_pack_blocks + kScanChunk - 1) / kScanChunk; }
 
 }  // namespace phmm

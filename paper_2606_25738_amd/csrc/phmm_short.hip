@@ -61,14 +61,29 @@ __device__ __forceinline__ const double* pow_table<double>(const Tables& t, int 
 
 constexpr int words_for(int n) { return (n + 3) / 4; }
 
-// FP32 instantiation: walks the FP32 packs of class CLS and queues rejected
-// pairs as FP64 items.  FP64 instantiation: walks the FP64 items of class
-// CLS (plain packs first, then reruns).
-template <typename R, int CLS>
-__global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Policy pol)
+// Waves per SIMD the fast FP32 kernel of a class is compiled for: the
+// register budget of 4 waves (128 VGPRs) holds classes up to N = 14 without
+// spills, that of 3 waves (168) the wider ones.  Other kernels: no target.
+template <typename R, int CLS, int KIND>
+constexpr int waves_target()
+{
+    return KIND != kFast32 ? 1 : CLS <= 5 ? 4 : 3;
+}
+
+// KIND kFast32 (R = float): walks the FP32 packs of class CLS; a pack whose
+// read has more than one gap byte, a gap byte of 0 or an insertion byte
+// above the scaled form's limit is deferred to the general FP32 kernel.
+// KIND kGen32 (R = float): walks the deferred packs of the class.  Both FP32
+// kernels queue pairs under the acceptance threshold as FP64 items.
+// KIND kAll64 (R = double): walks the plain FP64 packs of the class, then
+// the rerun items.
+template <typename R, int CLS, int KIND>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_target<R, CLS, KIND>())))
+void short_kernel(Batch b, Tables t, Work w, Policy pol)
 {
     constexpr int N = class_n(CLS);
     constexpr bool kFP32 = sizeof(R) == 4;
+    constexpr bool kFast = KIND == kFast32;
     __shared__ RowRec<R> rec[kWave];
     __shared__ int rinfo[kWave];  // read-base class mask | gcp byte << 16
     __shared__ int sflag[kWave];
@@ -76,10 +91,12 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
 
     const int lane = (int)threadIdx.x;
     Counters* ctr = w.ctr;
-    uint32_t* cursor = kFP32 ? &ctr->cursor32[CLS] : &ctr->cursor64[CLS];
+    uint32_t* cursor = &ctr->cursor[KIND][CLS];
     // FP64: the class's plain FP64 packs first, then the rerun items
     const uint32_t n_plain = ctr->pack_cnt[1][CLS];
-    const uint32_t count = kFP32 ? ctr->pack_cnt[0][CLS] : n_plain + ctr->item_cnt[CLS];
+    const uint32_t count = KIND == kFast32 ? ctr->pack_cnt[0][CLS]
+                         : KIND == kGen32  ? ctr->defer_cnt[CLS]
+                                           : n_plain + ctr->item_cnt[CLS];
 
     for (;;) {
         uint32_t it = 0;
@@ -88,8 +105,9 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
         if (it >= count) break;
 
         uint32_t pack_gi, mask;
-        if (kFP32) {
-            pack_gi = ctr->pack_base[0][CLS] + it;
+        if (KIND == kFast32 || KIND == kGen32) {
+            pack_gi = KIND == kFast32 ? ctr->pack_base[0][CLS] + it
+                                      : w.deferred[ctr->item_base[CLS] + it];
             const uint32_t np = w.packs[pack_gi].npairs;
             mask = np == 32 ? 0xffffffffu : ((1u << np) - 1u);
         } else if (it < n_plain) {
@@ -105,6 +123,32 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
         pack_gi = wave_broadcast0(pack_gi);
         mask = wave_broadcast0(mask);
         const bool rerun_item = !kFP32 && it >= n_plain;
+
+        // ---- read and its gap-continuation profile.  Scaled form possible:
+        // T_IM > 0 (gap byte >= 1) and bounded insertion bytes on every row.
+        const uint32_t r = b.pairs[2 * (uint64_t)pair0];
+        const uint64_t roff = b.read_off[r];
+        const int l = (int)(b.read_off[r + 1] - roff);
+        const int g0 = b.gq[roff];
+        bool varying = false, sc_ok = true;
+        for (int i0 = 0; i0 < l; i0 += kWave) {
+            const int i = i0 + lane;
+            const int gc = i < l ? (int)b.gq[roff + i] : g0;
+            const int ic = i < l ? (int)b.iq[roff + i] : 0;
+            varying = varying || __ballot(gc != g0) != 0ull;
+            sc_ok = sc_ok && __ballot(gc == 0 || ic > kScMaxInsQ) == 0ull;
+        }
+        if (kFast && (varying || !sc_ok)) {
+            if (lane == 0) {
+                const uint32_t idx = atomicAdd(&ctr->defer_cnt[CLS], 1u);
+                w.deferred[ctr->item_base[CLS] + idx] = pack_gi;
+            }
+            continue;
+        }
+        if (kFast) {  // known from here on: one gap byte, scaled form
+            varying = false;
+            sc_ok = true;
+        }
 
         // ---- segment layout: lanes [start_s, start_s + ceil(k_s/N)) per pair s
         const int nseg = __builtin_popcount(mask);
@@ -156,21 +200,6 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
             hc[n / 4] |= code << (8 * (n % 4));
         }
 
-        // ---- read and its gap-continuation profile
-        const uint32_t r = b.pairs[2 * (uint64_t)pair0];
-        const uint64_t roff = b.read_off[r];
-        const int l = (int)(b.read_off[r + 1] - roff);
-        const int g0 = b.gq[roff];
-        // scaled form possible: T_IM > 0 (gap byte >= 1) and bounded insertion
-        // bytes on every row
-        bool varying = false, sc_ok = true;
-        for (int i0 = 0; i0 < l; i0 += kWave) {
-            const int i = i0 + lane;
-            const int gc = i < l ? (int)b.gq[roff + i] : g0;
-            const int ic = i < l ? (int)b.iq[roff + i] : 0;
-            varying = varying || __ballot(gc != g0) != 0ull;
-            sc_ok = sc_ok && __ballot(gc == 0 || ic > kScMaxInsQ) == 0ull;
-        }
         const R notstart = (lane != segstart) ? (R)1 : (R)0;
         const R minit = real ? (R)(ldexp(1.0, ScaleOf<R>::exp) / (double)k) : (R)0;
         const R* pw = pow_table<R>(t, CLS, g0);
@@ -237,10 +266,14 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
                 }
             }
         };
-        if (sc_ok)
+        if constexpr (kFast) {
             run_rows(std::true_type{});
-        else
-            run_rows(std::false_type{});
+        } else {
+            if (sc_ok)
+                run_rows(std::true_type{});
+            else
+                run_rows(std::false_type{});
+        }
 
         // ---- eq.4: S = sum_j M(l,j) + I(l,j) over the real columns
         R s = (R)0;
@@ -289,48 +322,50 @@ __global__ __launch_bounds__(64) void short_kernel(Batch b, Tables t, Work w, Po
 }
 
 // ---------------------------------------------------------------- launchers
-template <typename R, int CLS>
+template <int KIND, int CLS>
 static void launch_one(int cls, dim3 grid, hipStream_t s, const Batch& b, const Tables& t,
                        const Work& w, const Policy& p)
 {
-    if (cls == CLS) hipLaunchKernelGGL((short_kernel<R, CLS>), grid, dim3(kWave), 0, s, b, t, w, p);
+    using R = typename std::conditional<KIND == kAll64, double, float>::type;
+    if (cls == CLS) hipLaunchKernelGGL((short_kernel<R, CLS, KIND>), grid, dim3(kWave), 0, s, b, t, w, p);
 }
 
-template <typename R, int... CLS>
+template <int KIND, int... CLS>
 static void launch_dispatch(int cls, dim3 grid, hipStream_t s, const Batch& b, const Tables& t,
                             const Work& w, const Policy& p, std::integer_sequence<int, CLS...>)
 {
-    (launch_one<R, CLS>(cls, grid, s, b, t, w, p), ...);
+    (launch_one<KIND, CLS>(cls, grid, s, b, t, w, p), ...);
 }
 
-void launch_short(bool fp32, int cls, int grid, hipStream_t s, const Batch& b, const Tables& t,
+void launch_short(int kind, int cls, int grid, hipStream_t s, const Batch& b, const Tables& t,
                   const Work& w, const Policy& p)
 {
-    if (fp32)
-        launch_dispatch<float>(cls, dim3(grid), s, b, t, w, p,
-                               std::make_integer_sequence<int, kNumClasses>{});
-    else
-        launch_dispatch<double>(cls, dim3(grid), s, b, t, w, p,
-                                std::make_integer_sequence<int, kNumClasses>{});
+    const auto seq = std::make_integer_sequence<int, kNumClasses>{};
+    if (kind == kFast32) launch_dispatch<kFast32>(cls, dim3(grid), s, b, t, w, p, seq);
+    else if (kind == kGen32) launch_dispatch<kGen32>(cls, dim3(grid), s, b, t, w, p, seq);
+    else launch_dispatch<kAll64>(cls, dim3(grid), s, b, t, w, p, seq);
 }
 
-template <typename R, int CLS>
+template <int KIND, int CLS>
 static const void* kernel_ptr_one(int cls)
 {
-    return cls == CLS ? reinterpret_cast<const void*>(&short_kernel<R, CLS>) : nullptr;
+    using R = typename std::conditional<KIND == kAll64, double, float>::type;
+    return cls == CLS ? reinterpret_cast<const void*>(&short_kernel<R, CLS, KIND>) : nullptr;
 }
-template <typename R, int... CLS>
+template <int KIND, int... CLS>
 static const void* kernel_ptr(int cls, std::integer_sequence<int, CLS...>)
 {
     const void* r = nullptr;
-    ((r = r ? r : kernel_ptr_one<R, CLS>(cls)), ...);
+    ((r = r ? r : kernel_ptr_one<KIND, CLS>(cls)), ...);
     return r;
 }
 
-const void* short_kernel_ptr(bool fp32, int cls)
+const void* short_kernel_ptr(int kind, int cls)
 {
-    return fp32 ? kernel_ptr<float>(cls, std::make_integer_sequence<int, kNumClasses>{})
-                : kernel_ptr<double>(cls, std::make_integer_sequence<int, kNumClasses>{});
+    const auto seq = std::make_integer_sequence<int, kNumClasses>{};
+    return kind == kFast32 ? kernel_ptr<kFast32>(cls, seq)
+         : kind == kGen32  ? kernel_ptr<kGen32>(cls, seq)
+                           : kernel_ptr<kAll64>(cls, seq);
 }
 
 }  // namespace phmm
