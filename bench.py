@@ -282,6 +282,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1,
                     help="timed steps of the plain FP64 path on the same batch (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default pack cost model instead of measuring it")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the served Poisson stream (0 = no serving leg)")
     ap.add_argument("--serve-load", type=float, default=0.8,
@@ -344,6 +346,21 @@ def main():
     peak32, peak64 = phmm.phmm_vector_peak(0)
     log("measured vector FMA peak: FP32 %.1f TFLOP/s, FP64 %.1f TFLOP/s" % (peak32, peak64))
     ctx = phmm.Context(timing=True)
+    costs = None
+    if not args.no_autotune:
+        # per-class costs measured on a synthetic batch, then the table that
+        # runs a sample of this workload (its first 20,000 regions) fastest
+        t = time.perf_counter()
+        ctx.autotune(seed=0)
+        ns = min(args.regions, 20000)
+        sb = synth.generate("cfg3", 0, ns)
+        sdb = phmm.DeviceBatch(sb, "cuda:0")
+        sws = torch.empty(phmm.phmm_workspace_bytes(ctx, len(sb["pair_list"]), sdb.max_read_len,
+                                                    sdb.max_hap_len), dtype=torch.uint8, device="cuda:0")
+        costs = ctx.autotune_sample(sdb, sws, stream)
+        del sdb, sws, sb
+        log("autotuned pack costs in %.2fs (FP32 table): %s"
+            % (time.perf_counter() - t, np.round(costs[0], 2).tolist()))
     ws = torch.empty(phmm.phmm_workspace_bytes(ctx, n_pairs, db.max_read_len, db.max_hap_len),
                      dtype=torch.uint8, device="cuda:0")
     copy_gbs = None
@@ -391,6 +408,8 @@ def main():
     fp64 = None
     if args.fp64_steps > 0:
         ctx64 = phmm.Context(precision=phmm.PHMM_FP64_PLAIN, timing=True)
+        if costs is not None:
+            ctx64.set_class_costs(costs)
         out64 = torch.empty_like(out)
         fl64 = torch.empty_like(fl)
         e64, ph64 = time_steps(phmm, torch, ctx64, db, out64, fl64, ws, stream, 1, args.fp64_steps)
@@ -428,6 +447,8 @@ def main():
         phases_ms={k: round(v, 3) for k, v in ph.items()},
         rerun_pairs=int(counts["rerun_pairs"]), rerun_fraction=counts["rerun_pairs"] / max(1, n_pairs),
         lane_utilisation=round(cells32 / max(1, counts["lane_columns"] * 150), 4),
+        pack_costs=None if costs is None else dict(fp32=np.round(costs[0], 3).tolist(),
+                                                   fp64=np.round(costs[1], 3).tolist()),
         fp64_plain=fp64, parity_sample=parity, serving=serving,
     )
     print(json.dumps(rec), flush=True)

@@ -93,6 +93,12 @@ typedef struct phmm_options {
     int one_pair_per_wave;  /* 1: no packing, every pair gets its own wavefront      */
     uint32_t fp32_max_rows; /* reads longer than this go straight to FP64 (FP32
                                rounding bias grows with the row count); default 2048 */
+    uint32_t long_fp32_max_rows; /* long pairs (haplotype > 64 x 24) with reads up to
+                               this many rows run in FP32 with rescaling, longer ones
+                               in FP64; default 4096.  The FP32 error grows with the
+                               row count (per-row coefficients are rounded once):
+                               measured 2.5e-4 in log10 at 32k rows, so about
+                               3e-5 at the default                                 */
     uint32_t watchdog_spins;/* long kernel: polls of a neighbour tile before giving
                                up with PHMM_ETIMEOUT; 0 = default                     */
     int timing;             /* 1: record per-phase HIP events (phmm_last_timing)     */
@@ -217,9 +223,10 @@ typedef struct phmm_counts {
     uint64_t packs_fp64;   /* wavefront packs run in FP64 (plain mode) */
     uint64_t rerun_items;  /* FP32 packs with at least one rerun pair  */
     uint64_t rerun_pairs;  /* pairs recomputed in FP64                 */
-    uint64_t long_pairs;   /* pairs sent to the long-pair kernel       */
+    uint64_t long_pairs;   /* pairs sent to the long-pair kernels      */
     uint64_t long_tiles;   /* wavefront tiles of the long-pair kernel  */
     uint64_t lane_columns; /* sum over packs of 64*N (occupied cells per row) */
+    uint64_t long_pairs_fp32; /* of those, run by the FP32 long kernel */
     uint64_t deferred_packs; /* FP32 packs run by the general FP32 kernel (a read
                                 with several gap bytes, a gap byte of 0 or an
                                 insertion byte above 65)                     */
@@ -236,6 +243,31 @@ typedef struct phmm_timing {
     float total_ms;    /* whole call                              */
 } phmm_timing;
 int phmm_last_timing(phmm_ctx* ctx, phmm_timing* out);
+
+/*
+ * Pack-shape tuning.  The packer chooses, for the pairs of each read, the
+ * column class N (columns per lane) that minimises (wavefronts needed) x
+ * cost[precision][class].  The default cost of a wavefront-row is N + 3 (N
+ * cells plus the scan).  phmm_autotune replaces the table of `ctx` by the
+ * time (ns) of one wavefront-row of each class's kernel on this device,
+ * measured on a synthetic batch in which every pair fills a wavefront exactly
+ * (this takes a few tenths of a second and runs on the context's stream;
+ * nothing else may use the context meanwhile).  costs / out_costs hold 2 x
+ * phmm_num_classes() floats: FP32 kernels first, then FP64.  Errors:
+ * PHMM_EINVAL (NULL, non-positive cost), PHMM_EDEVICE.
+ */
+int phmm_autotune(phmm_ctx* ctx, uint64_t seed, float* out_costs /* NULL ok */);
+
+/* Pack-shape tuning on the caller's own workload: times a sample batch (device
+ * buffers as phmm_forward_batch_async, with its workspace and stream) under
+ * the context's current cost table and under the family cost = N + a for
+ * a in {0, 1, 2, 3, 5, 8, 12, 20}, and keeps the fastest table.  It runs the
+ * sample 27 times; results written to the sample's outputs are discarded (a
+ * scratch output buffer is allocated for the duration of the call). */
+int phmm_autotune_sample(phmm_ctx* ctx, const phmm_device_batch* sample, void* d_workspace,
+                         size_t ws_bytes, void* hip_stream, float* out_costs /* NULL ok */);
+int phmm_set_class_costs(phmm_ctx* ctx, const float* costs);
+int phmm_get_class_costs(phmm_ctx* ctx, float* costs);
 
 /* Calibration: measures the device's achievable vector FMA rates (FP32
  * scalar FMA and FP64 FMA, TFLOP/s with an FMA counted as two flops) with

@@ -39,7 +39,8 @@ class PhmmError(RuntimeError):
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("accept_min_sum", ctypes.c_double),
                 ("force_class", ctypes.c_int), ("one_pair_per_wave", ctypes.c_int),
-                ("fp32_max_rows", ctypes.c_uint32), ("watchdog_spins", ctypes.c_uint32),
+                ("fp32_max_rows", ctypes.c_uint32), ("long_fp32_max_rows", ctypes.c_uint32),
+                ("watchdog_spins", ctypes.c_uint32),
                 ("timing", ctypes.c_int)]
 
 
@@ -56,7 +57,8 @@ class _DeviceBatch(ctypes.Structure):
 class _Counts(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("packs_fp32", "packs_fp64", "rerun_items",
                                                 "rerun_pairs", "long_pairs", "long_tiles",
-                                                "lane_columns", "deferred_packs")]
+                                                "lane_columns", "long_pairs_fp32",
+                                                "deferred_packs")]
 
 
 class _ServerOptions(ctypes.Structure):
@@ -130,6 +132,12 @@ def lib():
                                            ctypes.POINTER(ctypes.c_double)]
             L.phmm_copy_calib.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                           ctypes.c_void_p]
+            fp = ctypes.POINTER(ctypes.c_float)
+            L.phmm_autotune.argtypes = [vp, ctypes.c_uint64, fp]
+            L.phmm_set_class_costs.argtypes = [vp, fp]
+            L.phmm_autotune_sample.argtypes = [vp, ctypes.POINTER(_DeviceBatch), vp, ctypes.c_size_t,
+                                               vp, fp]
+            L.phmm_get_class_costs.argtypes = [vp, fp]
             L.phmm_server_default_options.argtypes = [ctypes.POINTER(_ServerOptions)]
             L.phmm_server_default_options.restype = None
             L.phmm_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int,
@@ -182,6 +190,7 @@ class Context:
     def __init__(self, device: int = 0, precision: int = PHMM_FP32_RERUN,
                  accept_min_sum: float | None = None, force_class: int = -1,
                  one_pair_per_wave: bool = False, fp32_max_rows: int | None = None,
+                 long_fp32_max_rows: int | None = None,
                  watchdog_spins: int = 0, timing: bool = False):
         L = lib()
         o = _Options()
@@ -193,6 +202,8 @@ class Context:
         o.one_pair_per_wave = int(bool(one_pair_per_wave))
         if fp32_max_rows is not None:
             o.fp32_max_rows = fp32_max_rows
+        if long_fp32_max_rows is not None:
+            o.long_fp32_max_rows = long_fp32_max_rows
         o.watchdog_spins = watchdog_spins
         o.timing = int(bool(timing))
         h = ctypes.c_void_p()
@@ -203,6 +214,35 @@ class Context:
     @property
     def handle(self):
         return self._h
+
+    def autotune(self, seed: int = 0) -> np.ndarray:
+        """Measure the per-class wavefront-row costs on this device and use them
+        for packing; returns them as a (2, n_classes) array (FP32, FP64), ns."""
+        c = np.zeros(2 * phmm_num_classes(), np.float32)
+        _check(lib().phmm_autotune(self._h, seed, c.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return c.reshape(2, -1)
+
+    def autotune_sample(self, db, workspace, stream=None) -> np.ndarray:
+        """Pick the cost table that runs a sample of the real workload (a
+        DeviceBatch) fastest; returns it as a (2, n_classes) array."""
+        c = np.zeros(2 * phmm_num_classes(), np.float32)
+        st = db.struct()
+        h = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        _check(lib().phmm_autotune_sample(self._h, ctypes.byref(st), workspace.data_ptr(),
+                                          workspace.numel() * workspace.element_size(), h,
+                                          c.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return c.reshape(2, -1)
+
+    def class_costs(self) -> np.ndarray:
+        c = np.zeros(2 * phmm_num_classes(), np.float32)
+        _check(lib().phmm_get_class_costs(self._h, c.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return c.reshape(2, -1)
+
+    def set_class_costs(self, costs) -> None:
+        c = np.ascontiguousarray(np.asarray(costs, np.float32).reshape(-1))
+        if c.size != 2 * phmm_num_classes():
+            raise ValueError("set_class_costs: need 2 x %d costs" % phmm_num_classes())
+        _check(lib().phmm_set_class_costs(self._h, c.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
 
     def close(self):
         if getattr(self, "_h", None):

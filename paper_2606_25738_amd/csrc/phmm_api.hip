@@ -21,10 +21,11 @@ const void* short_kernel_ptr(int kind, int cls);
 __global__ void reset_kernel(Counters* c);
 void launch_pack(hipStream_t s, const Batch& b, const Work& w, const Policy& pol);
 uint32_t scan_chunks(uint32_t n_pack_blocks);
-void launch_long(hipStream_t s, int grid, const Batch& b, const Tables& t, const Work& w,
-                 const Policy& p);
-const void* long_kernel_ptr();
+void launch_long(hipStream_t s, const int (&grid)[2], const Batch& b, const Tables& t,
+                 const Work& w, const Policy& p);
+const void* long_kernel_ptr(bool fp32);
 __host__ __device__ uint32_t long_slots(int grid);
+size_t long_ring_slot_bytes();
 }  // namespace phmm
 
 using namespace phmm;
@@ -71,6 +72,7 @@ extern "C" void phmm_default_options(phmm_options* o)
     o->force_class = -1;
     o->one_pair_per_wave = 0;
     o->fp32_max_rows = 2048;
+    o->long_fp32_max_rows = 4096;
     o->watchdog_spins = 0;
     o->timing = 0;
 }
@@ -82,20 +84,22 @@ struct phmm_ctx {
     hipStream_t stream = nullptr;
     int cus = 0;
     int grid_short[kNumKernelKinds][kNumClasses] = {};  // persistent wavefronts per kernel
-    int grid_long = 0;
+    int grid_long[2] = {};  // persistent wavefronts of the FP32 and FP64 long kernels
     double* d_p64 = nullptr;
     double* d_pw64 = nullptr;
     float* d_pw32 = nullptr;
-    double* d_pwlong = nullptr;
     // synchronous-API arena
     void* arena = nullptr;
     size_t arena_bytes = 0;
     // timing
     hipEvent_t ev[6] = {};
     bool timed = false;
+    // relative cost of one wavefront-row per (precision, class): N + 3 until
+    // phmm_autotune or phmm_set_class_costs replaces it
+    float cost[2][kNumClasses] = {};
 };
 
-static Policy make_policy(const phmm_options& o)
+static Policy make_policy(const phmm_options& o, const float (&cost)[2][kNumClasses])
 {
     Policy p;
     memset(&p, 0, sizeof p);
@@ -103,11 +107,11 @@ static Policy make_policy(const phmm_options& o)
     p.force_class = o.force_class;
     p.one_pair_per_wave = o.one_pair_per_wave;
     p.fp32_max_rows = o.fp32_max_rows;
+    p.long_fp32_max_rows = o.long_fp32_max_rows;
     p.accept_min_sum = (float)o.accept_min_sum;
     p.watchdog_spins = o.watchdog_spins ? o.watchdog_spins : 4000000u;
     for (int prec = 0; prec < 2; ++prec)
-        for (int c = 0; c < kNumClasses; ++c)
-            p.cost[prec][c] = (float)class_n(c) + 3.0f;  // row cost ~ N cells + scan
+        for (int c = 0; c < kNumClasses; ++c) p.cost[prec][c] = cost[prec][c];
     return p;
 }
 
@@ -137,19 +141,12 @@ static int build_tables(phmm_ctx* c)
         }
     }
     for (size_t i = 0; i < pw64.size(); ++i) pw32[i] = (float)pw64[i];
-    std::vector<double> pwl((size_t)256 * kPowStride);
-    for (int q = 0; q < 256; ++q) {
-        for (int m = 0; m <= 64; ++m) pwl[(size_t)q * kPowStride + m] = pow(p64[q], (double)(kLongN * m));
-        pwl[(size_t)q * kPowStride + 65] = pow(p64[q], (double)(kLongN - 1));
-    }
     HIP_TRY(hipMalloc(&c->d_p64, p64.size() * 8));
     HIP_TRY(hipMalloc(&c->d_pw64, pw64.size() * 8));
     HIP_TRY(hipMalloc(&c->d_pw32, pw32.size() * 4));
-    HIP_TRY(hipMalloc(&c->d_pwlong, pwl.size() * 8));
     HIP_TRY(hipMemcpy(c->d_p64, p64.data(), p64.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->d_pw64, pw64.data(), pw64.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->d_pw32, pw32.data(), pw32.size() * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->d_pwlong, pwl.data(), pwl.size() * 8, hipMemcpyHostToDevice));
     return PHMM_OK;
 }
 
@@ -162,7 +159,6 @@ extern "C" void phmm_destroy(phmm_ctx* c)
     (void)hipFree(c->d_p64);
     (void)hipFree(c->d_pw64);
     (void)hipFree(c->d_pw32);
-    (void)hipFree(c->d_pwlong);
     (void)hipFree(c->arena);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -183,6 +179,9 @@ static int create_impl(phmm_ctx* c, int device)
                     prop.gcnArchName);
     c->device = device;
     c->cus = prop.multiProcessorCount;
+    for (int prec = 0; prec < 2; ++prec)
+        for (int cls = 0; cls < kNumClasses; ++cls)
+            c->cost[prec][cls] = (float)class_n(cls) + 3.0f;  // row cost ~ N cells + scan
     HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     for (auto& e : c->ev) HIP_TRY(hipEventCreate(&e));
     for (int kind = 0; kind < kNumKernelKinds; ++kind)
@@ -192,9 +191,11 @@ static int create_impl(phmm_ctx* c, int device)
                 &per_cu, short_kernel_ptr(kind, cls), kWave, 0));
             c->grid_short[kind][cls] = std::max(1, per_cu) * c->cus;
         }
-    int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, long_kernel_ptr(), kWave, 0));
-    c->grid_long = std::max(1, per_cu) * c->cus;
+    for (int q = 0; q < 2; ++q) {
+        int per_cu = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, long_kernel_ptr(q == 0), kWave, 0));
+        c->grid_long[q] = std::max(1, per_cu) * c->cus;
+    }
     return build_tables(c);
 }
 
@@ -220,8 +221,8 @@ extern "C" int phmm_create(phmm_ctx** out, int device, const phmm_options* opt)
 
 // ---------------------------------------------------------------- workspace
 struct Layout {
-    size_t ctr, chunk_info, blk_cnt, blk_lc, chunk_part, packs, items, deferred, long_list,
-        long_pref, ring, slot, part, total;
+    size_t ctr, chunk_info, blk_cnt, blk_lc, chunk_part, packs, items, deferred, long_list32,
+        long_list64, long_pref, ring, slot, total;
 };
 
 static uint64_t pack_blocks(uint64_t n_pairs) { return (n_pairs + kPackBlock - 1) / kPackBlock; }
@@ -233,7 +234,7 @@ static Layout layout_for(const phmm_ctx* c, uint64_t n_pairs)
     Layout L;
     size_t o = 0;
     const uint64_t n = n_pairs ? n_pairs : 1;
-    const uint32_t slots = long_slots(c->grid_long);
+    const uint32_t slots = std::max(long_slots(c->grid_long[0]), long_slots(c->grid_long[1]));
     L.ctr = o; o = align256(o + sizeof(Counters));
     L.chunk_info = o; o = align256(o + n * 4);
     L.blk_cnt = o; o = align256(o + pack_blocks(n) * kSeg * 4);
@@ -242,11 +243,11 @@ static Layout layout_for(const phmm_ctx* c, uint64_t n_pairs)
     L.packs = o; o = align256(o + n * sizeof(Pack));
     L.items = o; o = align256(o + n * sizeof(Item));
     L.deferred = o; o = align256(o + n * 4);
-    L.long_list = o; o = align256(o + n * 4);
+    L.long_list32 = o; o = align256(o + n * 4);
+    L.long_list64 = o; o = align256(o + n * 4);
     L.long_pref = o; o = align256(o + (n + 1) * 4);
-    L.ring = o; o = align256(o + (size_t)slots * (kRing + 1) * 4 * sizeof(double));
+    L.ring = o; o = align256(o + (size_t)slots * long_ring_slot_bytes());
     L.slot = o; o = align256(o + (size_t)slots * 3 * sizeof(uint32_t));
-    L.part = o; o = align256(o + 64);
     L.total = o;
     return L;
 }
@@ -275,24 +276,22 @@ static Work work_for(phmm_ctx* c, void* ws, uint64_t n_pairs)
     w.packs = reinterpret_cast<Pack*>(base + L.packs);
     w.items = reinterpret_cast<Item*>(base + L.items);
     w.deferred = reinterpret_cast<uint32_t*>(base + L.deferred);
-    w.long_list = reinterpret_cast<uint32_t*>(base + L.long_list);
+    w.long_list[0] = reinterpret_cast<uint32_t*>(base + L.long_list32);
+    w.long_list[1] = reinterpret_cast<uint32_t*>(base + L.long_list64);
     w.long_pref = reinterpret_cast<uint32_t*>(base + L.long_pref);
     w.long_ring = reinterpret_cast<double*>(base + L.ring);
     w.long_prog = reinterpret_cast<uint32_t*>(base + L.slot);
-    w.long_part = reinterpret_cast<double*>(base + L.part);
-    w.max_long_tiles = long_slots(c->grid_long);
     return w;
 }
 
 // ---------------------------------------------------------------- launch
 static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s)
 {
-    const Policy pol = make_policy(c->opt);
+    const Policy pol = make_policy(c->opt, c->cost);
     Tables t;
     t.p64 = c->d_p64;
     t.pw64 = c->d_pw64;
     t.pw32 = c->d_pw32;
-    t.pwlong = c->d_pwlong;
     const Work w = work_for(c, ws, b.n_pairs);
     const bool timed = c->opt.timing != 0;
     if (timed) HIP_TRY(hipEventRecord(c->ev[0], s));
@@ -379,8 +378,9 @@ extern "C" int phmm_last_counts(phmm_ctx* c, void* d_ws, phmm_counts* out)
     }
     out->rerun_items = h.rerun_items;
     out->rerun_pairs = h.rerun_pairs;
-    out->long_pairs = h.n_long;
-    out->long_tiles = h.long_tiles;
+    out->long_pairs = (uint64_t)h.n_long[0] + h.n_long[1];
+    out->long_tiles = (uint64_t)h.long_tiles[0] + h.long_tiles[1];
+    out->long_pairs_fp32 = h.n_long[0];
     out->lane_columns = h.lane_columns;
     for (int k = 0; k < kNumClasses; ++k) out->deferred_packs += h.defer_cnt[k];
     return PHMM_OK;
@@ -557,4 +557,168 @@ extern "C" int phmm_forward_one(const uint8_t* read, const uint8_t* bq, const ui
     const uint32_t pl[2] = {0, 0};
     return phmm_forward_batch(g_default, read, bq, iq, dq, gq, ro, 1, hap, ho, 1, pl, 1,
                               out_log10, nullptr);
+}
+
+// ---------------------------------------------------------------- autotuning
+extern "C" int phmm_set_class_costs(phmm_ctx* c, const float* costs)
+{
+    if (!c || !costs) return fail(PHMM_EINVAL, "phmm_set_class_costs: NULL argument");
+    for (int i = 0; i < 2 * kNumClasses; ++i)
+        if (!(costs[i] > 0.0f) || !(costs[i] < 1e30f))
+            return fail(PHMM_EINVAL, "phmm_set_class_costs: cost %d is not a positive number", i);
+    for (int prec = 0; prec < 2; ++prec)
+        for (int cls = 0; cls < kNumClasses; ++cls) c->cost[prec][cls] = costs[prec * kNumClasses + cls];
+    return PHMM_OK;
+}
+
+extern "C" int phmm_get_class_costs(phmm_ctx* c, float* costs)
+{
+    if (!c || !costs) return fail(PHMM_EINVAL, "phmm_get_class_costs: NULL argument");
+    for (int prec = 0; prec < 2; ++prec)
+        for (int cls = 0; cls < kNumClasses; ++cls) costs[prec * kNumClasses + cls] = c->cost[prec][cls];
+    return PHMM_OK;
+}
+
+// Measures the time of one wavefront-row of every (precision, class) kernel
+// on a synthetic batch whose pairs fill a wavefront exactly in that class
+// (haplotypes of 64 N bases, one pair per pack, reads of 150 bases drawn from
+// the haplotypes so that no FP32 result falls under the acceptance
+// threshold), and makes those times the packer's cost table.
+extern "C" int phmm_autotune(phmm_ctx* c, uint64_t seed, float* out_costs)
+{
+    if (!c) return fail(PHMM_EINVAL, "phmm_autotune: ctx is NULL");
+    HIP_TRY(hipSetDevice(c->device));
+    constexpr int kReads = 512, kHaps = 16, kRepeat = 8, kLen = 150;
+    const uint64_t n_pairs = (uint64_t)kReads * kHaps * kRepeat;
+    uint64_t st = seed * 0x9E3779B97F4A7C15ull + 0xD1B54A32D192ED03ull;
+    auto rnd = [&st]() {
+        st ^= st << 13; st ^= st >> 7; st ^= st << 17;
+        return st;
+    };
+    static const uint8_t kB[4] = {'A', 'C', 'G', 'T'};
+    float measured[2][kNumClasses];
+    const phmm_options saved = c->opt;
+    int rc = PHMM_OK;
+    for (int cls = 0; cls < kNumClasses && rc == PHMM_OK; ++cls) {
+        const int k = kWave * class_n(cls);
+        // haplotypes: one random sequence and variants of it with a few SNPs
+        std::vector<uint8_t> haps((size_t)kHaps * k);
+        for (int j = 0; j < k; ++j) haps[j] = kB[rnd() & 3];
+        for (int h = 1; h < kHaps; ++h) {
+            memcpy(&haps[(size_t)h * k], haps.data(), k);
+            for (int v = 0; v < 3; ++v) haps[(size_t)h * k + rnd() % k] = kB[rnd() & 3];
+        }
+        std::vector<uint64_t> ho(kHaps + 1), ro(kReads + 1);
+        for (int h = 0; h <= kHaps; ++h) ho[h] = (uint64_t)h * k;
+        std::vector<uint8_t> reads((size_t)kReads * kLen), bq(reads.size()), iq(reads.size(), 45),
+            dq(reads.size(), 45), gq(reads.size(), 10);
+        for (int r = 0; r < kReads; ++r) {
+            ro[r] = (uint64_t)r * kLen;
+            const int off = (int)(rnd() % (uint64_t)(k > kLen ? k - kLen : 1));
+            for (int i = 0; i < kLen; ++i) {
+                const int j = off + i;
+                reads[(size_t)r * kLen + i] = j < k ? haps[j] : kB[rnd() & 3];
+                bq[(size_t)r * kLen + i] = (uint8_t)(30 + rnd() % 11);
+            }
+        }
+        ro[kReads] = (uint64_t)kReads * kLen;
+        std::vector<uint32_t> pl(2 * n_pairs);
+        uint64_t p = 0;
+        for (int rep = 0; rep < kRepeat; ++rep)
+            for (int r = 0; r < kReads; ++r)
+                for (int h = 0; h < kHaps; ++h, ++p) {
+                    pl[2 * p] = (uint32_t)r;
+                    pl[2 * p + 1] = (uint32_t)h;
+                }
+        std::vector<double> out(n_pairs);
+        for (int prec = 0; prec < 2 && rc == PHMM_OK; ++prec) {
+            c->opt = saved;
+            c->opt.precision = prec == 0 ? PHMM_FP32_RERUN : PHMM_FP64_PLAIN;
+            c->opt.force_class = cls;
+            c->opt.one_pair_per_wave = 1;
+            c->opt.timing = 1;
+            float best = 0.f;
+            for (int rep = 0; rep < 3 && rc == PHMM_OK; ++rep) {  // first run warms up
+                rc = phmm_forward_batch(c, reads.data(), bq.data(), iq.data(), dq.data(), gq.data(),
+                                        ro.data(), kReads, haps.data(), ho.data(), kHaps, pl.data(),
+                                        n_pairs, out.data(), nullptr);
+                float ms = 0.f;
+                if (rc == PHMM_OK) {
+                    if (hipEventElapsedTime(&ms, c->ev[prec == 0 ? 1 : 2], c->ev[prec == 0 ? 2 : 3]) !=
+                        hipSuccess)
+                        rc = fail(PHMM_EDEVICE, "phmm_autotune: event timing failed");
+                }
+                if (rep > 0 && (best == 0.f || ms < best)) best = ms;
+            }
+            // one pack per pair, kLen rows per pack
+            measured[prec][cls] = best / (float)((double)n_pairs * kLen) * 1e6f;  // ns per wave-row
+        }
+    }
+    c->opt = saved;
+    if (rc != PHMM_OK) return rc;
+    for (int prec = 0; prec < 2; ++prec)
+        for (int cls = 0; cls < kNumClasses; ++cls) {
+            c->cost[prec][cls] = measured[prec][cls];
+            if (out_costs) out_costs[prec * kNumClasses + cls] = measured[prec][cls];
+        }
+    return PHMM_OK;
+}
+
+// Chooses the cost table that runs a sample of the caller's own workload
+// fastest: the synthetic per-class measurements above (if phmm_autotune ran)
+// and the family N + a for a in {0, 1, 2, 3, 5, 8, 12, 20}, each timed on the
+// sample (packing plus the short kernels of the context's precision, best of
+// two runs after one warm-up).
+extern "C" int phmm_autotune_sample(phmm_ctx* c, const phmm_device_batch* sample, void* d_ws,
+                                    size_t ws_bytes, void* hip_stream, float* out_costs)
+{
+    if (!c || !sample || !d_ws) return fail(PHMM_EINVAL, "phmm_autotune_sample: NULL argument");
+    HIP_TRY(hipSetDevice(c->device));
+    const float adds[] = {0.f, 1.f, 2.f, 3.f, 5.f, 8.f, 12.f, 20.f};
+    constexpr int kCand = 1 + (int)(sizeof(adds) / sizeof(adds[0]));
+    float cand[kCand][2][kNumClasses];
+    for (int prec = 0; prec < 2; ++prec)
+        for (int cls = 0; cls < kNumClasses; ++cls) {
+            cand[0][prec][cls] = c->cost[prec][cls];
+            for (int a = 0; a < kCand - 1; ++a) cand[a + 1][prec][cls] = (float)class_n(cls) + adds[a];
+        }
+    const int timing = c->opt.timing;
+    c->opt.timing = 1;
+    const int prec = c->opt.precision == PHMM_FP32_RERUN ? 0 : 1;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    double* out = nullptr;
+    uint8_t* fl = nullptr;
+    int rc = PHMM_OK;
+    if (hipMalloc(&out, (size_t)(sample->n_pairs ? sample->n_pairs : 1) * 9) != hipSuccess)
+        rc = fail(PHMM_ENOMEM, "phmm_autotune_sample: output buffer");
+    fl = reinterpret_cast<uint8_t*>(out + (sample->n_pairs ? sample->n_pairs : 1));
+    int best = 0;
+    float best_ms = 0.f;
+    float saved[2][kNumClasses];
+    memcpy(saved, c->cost, sizeof saved);
+    for (int k = 0; k < kCand && rc == PHMM_OK; ++k) {
+        memcpy(c->cost, cand[k], sizeof saved);
+        float t_best = 0.f;
+        for (int rep = 0; rep < 3 && rc == PHMM_OK; ++rep) {
+            rc = phmm_forward_batch_async(c, sample, out, fl, d_ws, ws_bytes, s);
+            if (rc != PHMM_OK) break;
+            float ms = 0.f;
+            if (hipEventSynchronize(c->ev[4]) != hipSuccess ||
+                hipEventElapsedTime(&ms, c->ev[0], c->ev[prec == 0 ? 2 : 3]) != hipSuccess)
+                rc = fail(PHMM_EDEVICE, "phmm_autotune_sample: event timing failed");
+            if (rep > 0 && (t_best == 0.f || ms < t_best)) t_best = ms;
+        }
+        if (rc == PHMM_OK && (k == 0 || t_best < best_ms)) {
+            best = k;
+            best_ms = t_best;
+        }
+    }
+    if (out) (void)hipFree(out);
+    c->opt.timing = timing;
+    memcpy(c->cost, rc == PHMM_OK ? cand[best] : saved, sizeof saved);
+    if (rc != PHMM_OK) return rc;
+    if (out_costs)
+        for (int q = 0; q < 2; ++q)
+            for (int cls = 0; cls < kNumClasses; ++cls) out_costs[q * kNumClasses + cls] = c->cost[q][cls];
+    return PHMM_OK;
 }

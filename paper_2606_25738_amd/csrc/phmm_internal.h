@@ -30,10 +30,9 @@ constexpr int kPackBlock = 256;                     // packer threads per workgr
 // (0..64) holds g^(N*m) with g = 10^(-q/10); entry 65 holds g^(N-1).
 constexpr int kPowStride = 66;
 
-// Long-pair kernel geometry: one wavefront per tile of kLongN * 64 columns.
-constexpr int kLongN = 16;
-constexpr int kLongTile = kLongN * kWave;
-constexpr int kRing = 512;  // rows of boundary records buffered per tile
+// Long-pair kernel: one wavefront per tile of 64 lanes x 16 columns; kRing
+// rows of boundary records buffered per tile.
+constexpr int kRing = 512;
 
 struct Pack {
     uint32_t pair_start;  // first pair (index into pair_list)
@@ -63,8 +62,8 @@ struct Counters {
     uint32_t item_cnt[kNumClasses];      // rerun items queued by the FP32 kernels
     uint32_t defer_cnt[kNumClasses];     // FP32 packs deferred to the general kernel
     uint32_t cursor[kNumKernelKinds][kNumClasses];  // next pack or item of each kernel
-    uint32_t n_long;
-    uint32_t long_tiles;
+    uint32_t n_long[2];                  // long pairs run in [0] FP32, [1] FP64
+    uint32_t long_tiles[2];
     uint32_t long_cursor;
     uint32_t status;                     // 0 or a PHMM_E* code (as uint32)
     uint32_t rerun_items;
@@ -92,7 +91,6 @@ struct Tables {
     const double* p64;     // 10^(-q/10), q = 0..255
     const double* pw64;    // kNumClasses x 256 x kPowStride
     const float* pw32;     // same, rounded to FP32
-    const double* pwlong;  // 256 x kPowStride for N = kLongN (FP64)
 };
 
 struct Work {
@@ -106,12 +104,10 @@ struct Work {
     Pack* packs;           // pack array, segments per (precision, class)
     Item* items;           // FP64 items, segments per class
     uint32_t* deferred;    // FP32 packs for the general kernel, segments per class
-    uint32_t* long_list;   // long pair indices
-    uint32_t* long_pref;   // n_long + 1 tile prefix
-    double* long_ring;     // per tile: kRing x 4 doubles
-    uint32_t* long_prog;   // per tile: rows consumed by the next tile
-    double* long_part;     // per tile: partial sum, exponent
-    uint32_t max_long_tiles;
+    uint32_t* long_list[2];  // long pair indices: [0] FP32, [1] FP64
+    uint32_t* long_pref;   // tile prefix of the list being run (n_long + 1)
+    double* long_ring;     // per slot: kRing x 4 records, then the final sum
+    uint32_t* long_prog;   // per slot: rows consumed, owner, done
 };
 
 // Sets the calling thread's phmm_last_error() message; returns code.
@@ -122,6 +118,7 @@ struct Policy {
     int force_class;        // -1 or class index
     int one_pair_per_wave;
     uint32_t fp32_max_rows;
+    uint32_t long_fp32_max_rows;
     float accept_min_sum;
     uint32_t watchdog_spins;
     float cost[2][kNumClasses];  // relative cost of one wavefront-row per class

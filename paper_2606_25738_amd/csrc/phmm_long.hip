@@ -1,41 +1,73 @@
-// Long-pair PairHMM forward kernel for gfx950 (FP64 with power-of-two
-// rescaling).
+// Long-pair PairHMM forward kernel for gfx950, in FP32 or FP64, with
+// power-of-two rescaling.
 //
 // A pair whose haplotype is too long for one wavefront is cut into tiles of
-// kLongTile = 64 lanes x kLongN columns.  Each tile is processed by one
-// wavefront of a persistent grid; tiles of a pair are handed out in column
-// order.  Per row, a tile needs from its left neighbour the row's last M and
-// I values and the inclusive delete-chain prefix S(i, c0-1) at its first
-// column: this replaces the paper's multi-block extension through thread-block
-// clusters and distributed shared memory (Section 3.4, last paragraphs), which
-// gfx950 does not have.  The neighbour publishes one record per row into a
-// ring buffer in global memory; consumer and producer form a skewed pipeline
-// (a look-back of depth one), so the hand-off latency is paid once per tile,
-// not once per row.
+// 64 lanes x N columns (N = 16).  Each tile is processed
+// by one wavefront of a persistent grid; tiles of a pair are handed out in
+// column order.  Per row, a tile needs from its left neighbour the row's last
+// M and I values and the inclusive delete-chain prefix S(i, c0-1) at its
+// first column: this replaces the paper's multi-block extension through
+// thread-block clusters and distributed shared memory (Section 3.4, last
+// paragraphs), which gfx950 does not have.  The neighbour publishes one
+// record per row into a ring buffer in global memory; consumer and producer
+// form a skewed pipeline (a look-back of depth one), so the hand-off latency
+// is paid once per tile, not once per row.
+//
+// The row recurrence is the short kernel's (scaled form when the read allows
+// it, plain form otherwise); all tiles of a pair use the same per-row
+// coefficients, so the records they exchange are in the same units.
 //
 // Validity without fences: every published value is non-negative, so its
 // sign bit carries the parity of the ring lap (row / kRing).  A reader
-// accepts a field only when its sign bit matches the lap it expects; the ring
-// starts out all -0.0.  Each field is written and read with relaxed
-// agent-scope atomics, so no release/acquire fence is needed per row.  Ring
-// ownership changes (once per tile) use release/acquire.
+// accepts a field only when its sign bit matches the lap it expects; the
+// owner of a ring slot clears it to -0.  Each field is written and read with
+// relaxed agent-scope atomics, so no release/acquire fence is needed per row.
+// Ring ownership changes (once per tile) use release/acquire.
 //
 // Rescaling (not part of the paper, which gives no underflow scheme for its
 // long reads): every kRescaleRows rows a tile multiplies its state by 2^-e,
 // e the exponent of its largest value, and adds e to an integer exponent E.
 // Values handed between tiles carry the producer's exponent and are brought
 // into the consumer's scale with ldexp; when a record lies more than
-// kRebaseBits above the consumer's scale the consumer first rebases to it.  The start row is D(0,j) = 1/k and the
-// result is log10(S) + E log10(2).
+// rebase_bits<R> above the consumer's scale the consumer first rebases to
+// it.  The start row is D(0,j) = 1/k; the tiles' last-row sums are combined
+// in FP64 with their exponents and the result is log10(S) + E log10(2).
+#include <type_traits>
+
 #include "phmm_dev.h"
 
 namespace phmm {
 
 constexpr int kRescaleRows = 8;
-constexpr long long kRebaseBits = 256;  // rebase when a neighbour's record is this far above
-constexpr double kExpBias = 1099511627776.0;  // 2^40: exponents stored as E + 2^40
+constexpr int kNoRec = -(1 << 30);  // no record (all fields 0)
+
+template <typename R>
+struct LongGeom;
+template <>
+struct LongGeom<float> {
+    static constexpr int N = 16;
+    static constexpr int cls = 6;                   // short-kernel class with N = 16 (scan tables)
+    static constexpr int rebase_bits = 48;          // converted records stay below 2^49
+    static constexpr float exp_bias = 8388608.0f;   // 2^23: exponents stored as E + 2^23 (exact)
+};
+template <>
+struct LongGeom<double> {
+    static constexpr int N = 16;
+    static constexpr int cls = 6;                   // N = 16
+    static constexpr int rebase_bits = 256;
+    static constexpr double exp_bias = 1099511627776.0;  // 2^40
+};
 
 __host__ __device__ uint32_t long_slots(int grid) { return 2u * (uint32_t)(grid > 0 ? grid : 1); }
+__host__ __device__ uint32_t long_tile_cols(bool fp32)
+{
+    return (uint32_t)(fp32 ? LongGeom<float>::N : LongGeom<double>::N) * kWave;
+}
+
+// Ring slot layout (bytes): kRing rows x 4 fields of R, then the tile's final
+// (sum, exponent) pair as two doubles at kRingRowBytes.
+constexpr size_t kRingRowBytes = (size_t)kRing * 4 * sizeof(double);
+constexpr size_t kRingSlotBytes = kRingRowBytes + 4 * sizeof(double);
 
 struct SlotState {
     uint32_t* prog;   // rows the consumer has taken from the ring
@@ -52,20 +84,26 @@ __device__ __forceinline__ SlotState slot_state(const Work& w, uint32_t nslot)
     return s;
 }
 
-__device__ __forceinline__ double* ring_of(const Work& w, uint32_t slot)
+__device__ __forceinline__ char* ring_of(const Work& w, uint32_t slot)
 {
-    return w.long_ring + (size_t)slot * (kRing + 1) * 4;
+    return reinterpret_cast<char*>(w.long_ring) + (size_t)slot * kRingSlotBytes;
 }
 
-__device__ __forceinline__ void st_relaxed(double* p, double v)
+// Bit patterns of R and the lap parity kept in the sign bit.
+template <typename R>
+using Bits = typename std::conditional<sizeof(R) == 4, uint32_t, uint64_t>::type;
+
+template <typename R>
+__device__ __forceinline__ void st_relaxed(R* p, R v)
 {
-    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), __builtin_bit_cast(uint64_t, v),
+    __hip_atomic_store(reinterpret_cast<Bits<R>*>(p), __builtin_bit_cast(Bits<R>, v),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ double ld_relaxed(const double* p)
+template <typename R>
+__device__ __forceinline__ R ld_relaxed(const R* p)
 {
-    return __builtin_bit_cast(double, __hip_atomic_load(reinterpret_cast<const uint64_t*>(p),
-                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    return __builtin_bit_cast(R, __hip_atomic_load(reinterpret_cast<const Bits<R>*>(p),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 template <int ORDER>
 __device__ __forceinline__ uint32_t ld_u32(const uint32_t* p)
@@ -79,19 +117,21 @@ __device__ __forceinline__ void st_u32(uint32_t* p, uint32_t v)
     __hip_atomic_store(p, v, ORDER, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ double with_parity(double v, uint32_t parity)
+template <typename R>
+__device__ __forceinline__ R with_parity(R v, uint32_t parity)
 {
-    uint64_t u = __builtin_bit_cast(uint64_t, v) & 0x7fffffffffffffffull;
-    return __builtin_bit_cast(double, u | ((uint64_t)parity << 63));
+    constexpr int top = 8 * sizeof(R) - 1;
+    const Bits<R> u = __builtin_bit_cast(Bits<R>, v) & ~((Bits<R>)1 << top);
+    return __builtin_bit_cast(R, u | ((Bits<R>)parity << top));
 }
-__device__ __forceinline__ uint32_t parity_of(double v)
+template <typename R>
+__device__ __forceinline__ uint32_t parity_of(R v)
 {
-    return (uint32_t)(__builtin_bit_cast(uint64_t, v) >> 63);
+    return (uint32_t)(__builtin_bit_cast(Bits<R>, v) >> (8 * sizeof(R) - 1));
 }
+__device__ __forceinline__ float magnitude(float v) { return __builtin_fabsf(v); }
 __device__ __forceinline__ double magnitude(double v) { return __builtin_fabs(v); }
 
-// Sets the device status (first error wins) and returns true if any wave
-// already failed.
 __device__ __forceinline__ bool aborted(const Work& w)
 {
     return ld_u32<__ATOMIC_RELAXED>(&w.ctr->status) != 0u;
@@ -101,20 +141,22 @@ __device__ __forceinline__ void raise_timeout(const Work& w)
     atomicCAS(&w.ctr->status, 0u, (uint32_t)(-5));  // PHMM_ETIMEOUT
 }
 
-// Tile prefix over the long pairs, and reset of the ring ownership state.
-__global__ void long_prefix_kernel(Batch b, Work w, uint32_t nslot)
+// Tile prefix over the long pairs of list `which`, and reset of the ring
+// ownership state.
+__global__ void long_prefix_kernel(Batch b, Work w, uint32_t nslot, int which, uint32_t tile_cols)
 {
     __shared__ uint32_t part[256];
-    const uint32_t n = w.ctr->n_long;
+    const uint32_t n = w.ctr->n_long[which];
+    const uint32_t* list = w.long_list[which];
     const int t = (int)threadIdx.x;
     const uint32_t per = (n + 255u) / 256u;
     const uint32_t lo = (uint32_t)t * per, hi = lo + per < n ? lo + per : n;
     uint32_t sum = 0;
     for (uint32_t s = lo; s < hi; ++s) {
-        const uint32_t pair = w.long_list[s];
+        const uint32_t pair = list[s];
         const uint32_t h = b.pairs[2 * (uint64_t)pair + 1];
         const uint32_t k = (uint32_t)(b.hap_off[h + 1] - b.hap_off[h]);
-        sum += (k + kLongTile - 1) / kLongTile;
+        sum += (k + tile_cols - 1) / tile_cols;
     }
     part[t] = sum;
     __syncthreads();
@@ -125,7 +167,7 @@ __global__ void long_prefix_kernel(Batch b, Work w, uint32_t nslot)
             part[q] = acc;
             acc += v;
         }
-        w.ctr->long_tiles = acc;
+        w.ctr->long_tiles[which] = acc;
         w.ctr->long_cursor = 0;
         w.long_pref[n] = acc;
     }
@@ -133,60 +175,23 @@ __global__ void long_prefix_kernel(Batch b, Work w, uint32_t nslot)
     uint32_t acc = part[t];
     for (uint32_t s = lo; s < hi; ++s) {
         w.long_pref[s] = acc;
-        const uint32_t pair = w.long_list[s];
+        const uint32_t pair = list[s];
         const uint32_t h = b.pairs[2 * (uint64_t)pair + 1];
         const uint32_t k = (uint32_t)(b.hap_off[h + 1] - b.hap_off[h]);
-        acc += (k + kLongTile - 1) / kLongTile;
+        acc += (k + tile_cols - 1) / tile_cols;
     }
     for (uint32_t s = (uint32_t)t; s < 3 * nslot; s += 256) w.long_prog[s] = 0u;
 }
 
-struct LRec {
-    double dp, px, tmm, tim, cd, tmi, tii, pm;
-};
-
-constexpr int kLongWords = kLongN / 4;
-
-__device__ __forceinline__ void lrow_first(double (&Mo)[kLongN], double (&Io)[kLongN],
-                                           const uint32_t (&hc)[kLongWords], int bidx,
-                                           const LRec& c, double minit, double g, double& Vp)
+template <typename R>
+__device__ __forceinline__ R rd_lane(R v, int lane);
+template <>
+__device__ __forceinline__ float rd_lane<float>(float v, int lane)
 {
-    double V = 0.0;
-    const double base = c.tim * minit;
-#pragma unroll
-    for (int n = 0; n < kLongN; ++n) {
-        const double p = emit_sel(hc[n / 4], 8 * (n % 4) + bidx, c.pm, c.px);
-        const double m = p * base;
-        Mo[n] = m;
-        Io[n] = 0.0;
-        if (n < kLongN - 1) V = __builtin_fma(g, V, m);
-    }
-    Vp = V;
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
 }
-
-__device__ __forceinline__ void lrow_step(const double (&Mi)[kLongN], const double (&Ii)[kLongN],
-                                          double (&Mo)[kLongN], double (&Io)[kLongN],
-                                          const uint32_t (&hc)[kLongWords], int bidx,
-                                          const LRec& c, double Mleft, double Ileft, double C,
-                                          double gprev, double gcur, double& Vp)
-{
-    double T = C, V = 0.0;
-#pragma unroll
-    for (int n = 0; n < kLongN; ++n) {
-        const double mprev = n == 0 ? Mleft : Mi[n - 1];
-        const double iprev = n == 0 ? Ileft : Ii[n - 1];
-        const double p = emit_sel(hc[n / 4], 8 * (n % 4) + bidx, c.pm, c.px);
-        const double x = __builtin_fma(c.cd, T, __builtin_fma(c.tim, iprev, c.tmm * mprev));
-        const double m = p * x;
-        Mo[n] = m;
-        Io[n] = __builtin_fma(c.tii, Ii[n], c.tmi * Mi[n]);
-        T = __builtin_fma(gprev, T, mprev);
-        if (n < kLongN - 1) V = __builtin_fma(gcur, V, m);
-    }
-    Vp = V;
-}
-
-__device__ __forceinline__ double rd_lane(double v, int lane)
+template <>
+__device__ __forceinline__ double rd_lane<double>(double v, int lane)
 {
     uint64_t u = __builtin_bit_cast(uint64_t, v);
     uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
@@ -215,16 +220,60 @@ __device__ __forceinline__ void acc_add(double& m1, long long& E1, double m2, lo
     else { m1 = m2 + ldexp(m1, (int)max(E1 - E2, -2000LL)); E1 = E2; }
 }
 
+__device__ __forceinline__ float maxR(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ double maxR(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ int exponent_of(float v) { int e; frexpf(v, &e); return e; }
+__device__ __forceinline__ int exponent_of(double v) { int e; frexp(v, &e); return e; }
+__device__ __forceinline__ float scale2(float v, int e) { return ldexpf(v, e); }
+__device__ __forceinline__ double scale2(double v, int e) { return ldexp(v, e); }
+
+// 2^e as an exact R when it is a normal number of R (|e| within the exponent
+// range), so that scaling is one multiply; callers fall back to ldexp outside.
+template <typename R>
+__device__ __forceinline__ bool pow2_ok(int e)
+{
+    return sizeof(R) == 4 ? (e >= -126 && e <= 127) : (e >= -1022 && e <= 1023);
+}
+__device__ __forceinline__ float pow2f(int e) { return __builtin_bit_cast(float, (uint32_t)(e + 127) << 23); }
+__device__ __forceinline__ double pow2d(int e)
+{
+    return __builtin_bit_cast(double, (uint64_t)(e + 1023) << 52);
+}
+template <typename R>
+__device__ __forceinline__ R pow2(int e);
+template <>
+__device__ __forceinline__ float pow2<float>(int e) { return pow2f(e); }
+template <>
+__device__ __forceinline__ double pow2<double>(int e) { return pow2d(e); }
+
+template <typename R>
+__device__ __forceinline__ const R* long_pow(const Tables& t, int gcp);
+template <>
+__device__ __forceinline__ const float* long_pow<float>(const Tables& t, int gcp)
+{
+    return t.pw32 + ((size_t)LongGeom<float>::cls * 256 + gcp) * kPowStride;
+}
+template <>
+__device__ __forceinline__ const double* long_pow<double>(const Tables& t, int gcp)
+{
+    return t.pw64 + ((size_t)LongGeom<double>::cls * 256 + gcp) * kPowStride;
+}
+
+// List `which` (0: FP32 pairs, 1: FP64 pairs) in precision R.
+template <typename R>
 __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Policy pol)
 {
-    constexpr int N = kLongN;
-    __shared__ LRec rec[kWave];
+    constexpr int N = LongGeom<R>::N;
+    constexpr uint32_t kTile = (uint32_t)N * kWave;
+    constexpr int which = sizeof(R) == 4 ? 0 : 1;
+    __shared__ RowRec<R> rec[kWave];
     __shared__ int rinfo[kWave];
     const int lane = (int)threadIdx.x;
     const uint32_t nslot = long_slots((int)gridDim.x);
     const SlotState ss = slot_state(w, nslot);
-    const uint32_t total = w.ctr->long_tiles;
-    const uint32_t n_long = w.ctr->n_long;
+    const uint32_t total = w.ctr->long_tiles[which];
+    const uint32_t n_long = w.ctr->n_long[which];
+    const uint32_t* list = w.long_list[which];
     const uint32_t spin_limit = pol.watchdog_spins;
 
     for (;;) {
@@ -243,14 +292,16 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
         const uint32_t tile = it - w.long_pref[s_idx];
         const uint32_t ntiles = w.long_pref[s_idx + 1] - w.long_pref[s_idx];
         const bool has_prod = tile > 0, has_cons = tile + 1 < ntiles;
-        const uint32_t pair = w.long_list[s_idx];
+        const uint32_t pair = list[s_idx];
         const uint32_t r = b.pairs[2 * (uint64_t)pair], h = b.pairs[2 * (uint64_t)pair + 1];
         const uint64_t roff = b.read_off[r], hoff = b.hap_off[h];
         const int l = (int)(b.read_off[r + 1] - roff);
         const uint32_t k = (uint32_t)(b.hap_off[h + 1] - hoff);
         const uint32_t slot = it % nslot, pslot = (it + nslot - 1) % nslot;
-        double* ring = ring_of(w, slot);
-        const double* pring = ring_of(w, pslot);
+        R* ring = reinterpret_cast<R*>(ring_of(w, slot));
+        const R* pring = reinterpret_cast<const R*>(ring_of(w, pslot));
+        double* fin = reinterpret_cast<double*>(ring_of(w, slot) + kRingRowBytes);
+        const double* pfin = reinterpret_cast<const double*>(ring_of(w, pslot) + kRingRowBytes);
 
         // ---- take over ring slot `slot` once its previous occupant's ring
         // (item it - nslot) has been read completely
@@ -265,7 +316,8 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
         }
         if (!dead) {
             if (has_cons) {
-                for (int q = lane; q < (kRing + 1) * 4; q += kWave) st_relaxed(ring + q, -0.0);
+                for (int q = lane; q < kRing * 4; q += kWave) st_relaxed(ring + q, (R)-0.0);
+                if (lane < 2) st_relaxed(fin + lane, -0.0);
                 if (lane == 0) st_u32<__ATOMIC_RELAXED>(&ss.prog[slot], 0u);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 if (lane == 0) st_u32<__ATOMIC_RELEASE>(&ss.owner[slot], it + 1u);
@@ -284,146 +336,87 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
         if (__ballot(dead) != 0ull) break;
 
         // ---- columns of this lane as 8-bit match codes, four per register
-        const uint32_t c0 = tile * (uint32_t)kLongTile + (uint32_t)lane * N;
-        uint32_t hc[kLongWords];
+        const uint32_t c0 = tile * kTile + (uint32_t)lane * N;
+        uint32_t hc[(N + 3) / 4];
 #pragma unroll
-        for (int q = 0; q < kLongWords; ++q) hc[q] = 0u;
+        for (int q = 0; q < (N + 3) / 4; ++q) hc[q] = 0u;
 #pragma unroll
         for (int n = 0; n < N; ++n) {
             const uint32_t j = c0 + (uint32_t)n;
             const uint32_t code = j < k ? hap_code(b.haps[hoff + j]) : kPadCode;
             hc[n / 4] |= code << (8 * (n % 4));
         }
-        const double minit = 1.0 / (double)k;
+        // read profile: scaled row form when every gap byte is >= 1 and every
+        // insertion byte within the form's limit
         const int g0 = b.gq[roff];
-        const double* pw0 = t.pwlong + (size_t)g0 * kPowStride;
-        ScanMul<double> mul = make_scan_mul<double>(pw0, lane, 0);
-        double gcur = t.p64[g0], gprev = gcur, gN1 = pw0[65], gN = pw0[1];
-        const ScanMul<double> ones = make_sum_mul<double>(lane, 0);
+        bool sc_ok = true;
+        for (int i0 = 0; i0 < l; i0 += kWave) {
+            const int i = i0 + lane;
+            const int gc = i < l ? (int)b.gq[roff + i] : g0;
+            const int ic = i < l ? (int)b.iq[roff + i] : 0;
+            sc_ok = sc_ok && __ballot(gc == 0 || ic > kScMaxInsQ) == 0ull;
+        }
+        const R minit = (R)(1.0 / (double)k);
+        const R* pw0 = long_pow<R>(t, g0);
+        ScanMul<R> mul = make_scan_mul<R>(pw0, lane, 0);
+        R gcur = (R)t.p64[g0], gprev = gcur, gN1 = pw0[65], gN = pw0[1];
+        int gc_cur = g0;
+        const ScanMul<R> ones = make_sum_mul<R>(lane, 0);
 
-        // rows alternate between the (Ma, Ia) and (Mb, Ib) register sets
-        double Ma[N], Ia[N], Mb[N], Ib[N];
+        R Ma[N], Ia[N], Mb[N], Ib[N];
 #pragma unroll
-        for (int n = 0; n < N; ++n) { Ma[n] = 0.0; Ia[n] = 0.0; Mb[n] = 0.0; Ib[n] = 0.0; }
-        double Mleft = 0.0, Ileft = 0.0, C = 0.0;
-        long long E = 0;
-        // producer records buffered one per lane: rows rb .. rb+nvalid-1
-        double bM = 0.0, bI = 0.0, bP = 0.0, bE = 0.0;
-        int rb = 0, nvalid = 0;
+        for (int n = 0; n < N; ++n) { Ma[n] = (R)0; Ia[n] = (R)0; Mb[n] = (R)0; Ib[n] = (R)0; }
+        R Mleft = (R)0, Ileft = (R)0, C = (R)0;
+        int E = 0;
         uint32_t prog_seen = 0;
 
-        for (int i0 = 0; i0 < l && !dead; i0 += kWave) {
-            __syncthreads();
-            {
-                const int i = i0 + lane;
-                if (i < l) {
-                    const uint64_t a = roff + (uint64_t)i;
-                    const double eps = t.p64[b.bq[a]];
-                    const double tmi = t.p64[b.iq[a]];
-                    const double tmd_prev = i > 0 ? t.p64[b.dq[a - 1]] : 0.0;
-                    const int gc = b.gq[a];
-                    const double g = t.p64[gc];
-                    const double tmd = t.p64[b.dq[a]];
-                    double tmm = 1.0 - (tmi + tmd);
-                    tmm = tmm < 0.0 ? 0.0 : tmm;
-                    const double pm = 1.0 - eps, px = eps / 3.0, tim = 1.0 - g;
-                    LRec rr;
-                    rr.dp = pm - px;
-                    rr.px = px;
-                    rr.tmm = tmm;
-                    rr.tim = tim;
-                    rr.cd = tim * tmd_prev;
-                    rr.tmi = tmi;
-                    rr.tii = g;
-                    rr.pm = pm;
-                    rec[lane] = rr;
-                    rinfo[lane] = read_base_index(b.reads[a]) | (gc << 16);
-                }
-            }
-            __syncthreads();
-            const int nrows = l - i0 < kWave ? l - i0 : kWave;
-            // one row: Mp/Ip name the register set that receives row i
-            auto do_row = [&](int tt, const double(&Mi)[N], const double(&Ii)[N], double(&Mp)[N],
-                              double(&Ip)[N]) -> bool {
-                const int i = i0 + tt;
-                const LRec c = rec[tt];
+        auto run_rows = [&](auto sc_tag) {
+            constexpr bool SC = decltype(sc_tag)::value;
+            // producer records of the current window, lane q holding row
+            // i0 + q in the producer's scale (magnitudes, exponent, and the
+            // exponent of the largest field: kNoRec when there is none)
+            R rM = (R)0, rI = (R)0, rP = (R)0;
+            int rE = 0, rTop = kNoRec;
+            // the current group's records brought to this tile's scale
+            R wM = (R)0, wI = (R)0, wP = (R)0;
+            // one row: Mp/Ip receive row i (window slot tt) from (Mi, Ii)
+            auto do_row = [&](int i, int tt, const R(&Mi)[N], const R(&Ii)[N], R(&Mp)[N],
+                              R(&Ip)[N]) -> bool {
+                const RowRec<R> c = rec[tt];
                 const int info = __builtin_amdgcn_readfirstlane(rinfo[tt]);
                 const int gc = info >> 16;
-                if (gc != g0 || gprev != gcur) {  // per-row gap continuation
-                    gprev = gcur;
-                    gcur = t.p64[gc];
-                    const double* pwi = t.pwlong + (size_t)gc * kPowStride;
-                    mul = make_scan_mul<double>(pwi, lane, 0);
+                gprev = gcur;
+                if (gc != gc_cur) {  // per-row gap continuation
+                    gc_cur = gc;
+                    gcur = (R)t.p64[gc];
+                    const R* pwi = long_pow<R>(t, gc);
+                    mul = make_scan_mul<R>(pwi, lane, 0);
                     gN1 = pwi[65];
                     gN = pwi[1];
                 }
-                double Vp;
+                R Vp;
                 const int bidx = info & 0xff;
-                if (i == 0) lrow_first(Mp, Ip, hc, bidx, c, minit, gcur, Vp);
-                else lrow_step(Mi, Ii, Mp, Ip, hc, bidx, c, Mleft, Ileft, C, gprev, gcur, Vp);
-                double nbM = 0.0, nbI = 0.0, nbP = 0.0;
-                if (has_prod) {
-                    if (i >= rb + nvalid) {  // refill the record buffer
-                        if (lane == 0) st_u32<__ATOMIC_RELAXED>(&ss.prog[pslot], (uint32_t)i);
-                        uint32_t spins = 0;
-                        for (;;) {
-                            const int row = i + lane;
-                            const uint32_t par = ((uint32_t)row / kRing) & 1u;
-                            const double* rp = pring + (size_t)((uint32_t)row % kRing) * 4;
-                            bool ok = false;
-                            if (row < l) {
-                                bM = ld_relaxed(rp + 0);
-                                bI = ld_relaxed(rp + 1);
-                                bP = ld_relaxed(rp + 2);
-                                bE = ld_relaxed(rp + 3);
-                                ok = parity_of(bM) == par && parity_of(bI) == par &&
-                                     parity_of(bP) == par && parity_of(bE) == par;
-                            }
-                            const uint64_t okm = __ballot(ok);
-                            const int lead = okm == ~0ull ? 64 : __builtin_ctzll(~okm);
-                            if (lead > 0) { rb = i; nvalid = lead; break; }
-                            if (++spins > spin_limit) { raise_timeout(w); dead = true; break; }
-                            if ((spins & 63u) == 0u && aborted(w)) { dead = true; break; }
-                            __builtin_amdgcn_s_sleep(1);
-                        }
-                        if (dead) return false;
-                    }
-                    const int q = i - rb;
-                    const long long Ep = (long long)(magnitude(rd_lane(bE, q)) - kExpBias);
-                    const double rM = magnitude(rd_lane(bM, q)), rI = magnitude(rd_lane(bI, q));
-                    const double rP = magnitude(rd_lane(bP, q));
-                    // Within a tile values fall by T_DD per column away from the
-                    // alignment band, so a neighbour's boundary can sit far above
-                    // this tile's scale (this tile's own values are then
-                    // negligible).  Rebase before converting so the record stays
-                    // representable.
-                    const double mrec = fmax(rM, fmax(rI, rP));
-                    if (mrec > 0.0) {
-                        int er;
-                        frexp(mrec, &er);
-                        if (Ep + er - E > kRebaseBits) {
-                            const long long enew = Ep + er;
-                            const double f = ldexp(1.0, (int)max(E - enew, -2000LL));
-#pragma unroll
-                            for (int n = 0; n < N; ++n) { Mp[n] *= f; Ip[n] *= f; }
-                            Vp *= f;
-                            E = enew;
-                        }
-                    }
-                    const int sh = (int)max(min(Ep - E, 2000LL), -2000LL);
-                    nbM = ldexp(rM, sh);
-                    nbI = ldexp(rI, sh);
-                    nbP = ldexp(rP, sh);
-                }
+                if (i == 0)
+                    row_first<R, N>(Mp, Ip, hc, bidx, c, minit, gcur, Vp);
+                else
+                    row_step<R, N, SC>(Mi, Ii, Mp, Ip, hc, bidx, c, Mleft, Ileft, C, gprev, gcur,
+                                       Vp);
+                // lane 0 takes the left neighbour's boundary (zero in the first
+                // tile) before the row's delete-chain window sums are formed
                 Mleft = dpp<kWaveShr1>(Mp[N - 1]);
                 Ileft = dpp<kWaveShr1>(Ip[N - 1]);
-                if (lane == 0) { Mleft = nbM; Ileft = nbI; }
-                const double vsh = __builtin_fma(gN1, Mleft, Vp);
-                double u = dpp<kWaveShr1>(vsh);
+                R nbP = (R)0;
+                if (has_prod) {
+                    const R nbM = rd_lane(wM, tt), nbI = rd_lane(wI, tt);
+                    nbP = rd_lane(wP, tt);
+                    if (lane == 0) { Mleft = nbM; Ileft = nbI; }
+                }
+                const R vsh = fmaR(gN1, Mleft, Vp);
+                R u = dpp<kWaveShr1>(vsh);
                 if (lane == 0) u = nbP;
                 C = seg_scan(u, mul);
                 if (has_cons) {  // publish row i for the next tile
-                    const double P = __builtin_fma(gN, C, vsh);
+                    const R P = fmaR(gN, C, vsh);
                     if (i >= kRing && (uint32_t)(i - kRing + 1) > prog_seen) {
                         uint32_t spins = 0;
                         for (;;) {
@@ -437,65 +430,154 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
                     }
                     if (lane == 63) {
                         const uint32_t par = ((uint32_t)i / kRing) & 1u;
-                        double* rp = ring + (size_t)((uint32_t)i % kRing) * 4;
+                        R* rp = ring + (size_t)((uint32_t)i % kRing) * 4;
                         st_relaxed(rp + 0, with_parity(Mp[N - 1], par));
                         st_relaxed(rp + 1, with_parity(Ip[N - 1], par));
                         st_relaxed(rp + 2, with_parity(P, par));
-                        st_relaxed(rp + 3, with_parity((double)E + kExpBias, par));
-                    }
-                }
-                if ((i % kRescaleRows) == kRescaleRows - 1) {
-                    double mx = C > Mleft ? C : Mleft;
-                    mx = mx > Ileft ? mx : Ileft;
-#pragma unroll
-                    for (int n = 0; n < N; ++n) {
-                        mx = mx > Mp[n] ? mx : Mp[n];
-                        mx = mx > Ip[n] ? mx : Ip[n];
-                    }
-                    int ex = 0;
-                    if (mx > 0.0) { frexp(mx, &ex); ex += 4096; }
-                    const int emax = wave_max_int(ex);
-                    if (emax > 0) {
-                        const int e = emax - 4096;
-                        const double f = ldexp(1.0, -e);
-#pragma unroll
-                        for (int n = 0; n < N; ++n) { Mp[n] *= f; Ip[n] *= f; }
-                        Mleft *= f;
-                        Ileft *= f;
-                        C *= f;
-                        E += e;
+                        st_relaxed(rp + 3, with_parity((R)((double)E + (double)LongGeom<R>::exp_bias), par));
                     }
                 }
                 return true;
             };
-            int tt = 0;
-            for (; tt + 1 < nrows; tt += 2) {
-                if (!do_row(tt, Ma, Ia, Mb, Ib)) break;
-                if (!do_row(tt + 1, Mb, Ib, Ma, Ia)) break;
-            }
-            if (!dead && tt < nrows) {
-                if (do_row(tt, Ma, Ia, Mb, Ib)) {
+            // every kRescaleRows rows: bring the row maximum to about 1 (a
+            // multiply by an exact power of two, done every time so that the
+            // row registers need no merge)
+            auto rescale = [&](R(&Mp)[N], R(&Ip)[N]) {
+                R mx = maxR(C, maxR(Mleft, Ileft));
 #pragma unroll
-                    for (int n = 0; n < N; ++n) { Ma[n] = Mb[n]; Ia[n] = Ib[n]; }
+                for (int n = 0; n < N; ++n) mx = maxR(mx, maxR(Mp[n], Ip[n]));
+                const int emax = wave_max_int(mx > (R)0 ? exponent_of(mx) + 4096 : 0);
+                int e = emax > 0 ? emax - 4096 : 0;
+                if (!pow2_ok<R>(-e)) e = e > 0 ? (sizeof(R) == 4 ? 126 : 1022) : -(sizeof(R) == 4 ? 126 : 1022);
+                const R f = pow2<R>(-e);
+#pragma unroll
+                for (int n = 0; n < N; ++n) {
+                    Mp[n] *= f;
+                    Ip[n] *= f;
+                }
+                Mleft *= f;
+                Ileft *= f;
+                C *= f;
+                E += e;
+            };
+            // Records of window rows tt .. tt+ng-1 to this tile's scale.  Within
+            // a tile values fall by T_DD per column away from the alignment
+            // band, so a neighbour's boundary can sit far above this tile's
+            // own, then negligible, values (a record stays exactly 0 in the
+            // neighbour until the band comes within range of its last column):
+            // the tile is first rebased to the largest of them when they lie
+            // more than rebase_bits above its scale.  Both steps are exact
+            // power-of-two scalings over the full exponent range (ldexp), so
+            // values far below the new scale flush to 0 and nothing overflows.
+            auto take_records = [&](int tt, int ng) {
+                const int rel = lane >= tt && lane < tt + ng && rTop != kNoRec ? rTop - E : kNoRec;
+                const int top = wave_max_int(rel - kNoRec + 1) - 1 + kNoRec;
+                if (top > LongGeom<R>::rebase_bits) {
+#pragma unroll
+                    for (int n = 0; n < N; ++n) {
+                        Ma[n] = scale2(Ma[n], -top);
+                        Ia[n] = scale2(Ia[n], -top);
+                    }
+                    Mleft = scale2(Mleft, -top);
+                    Ileft = scale2(Ileft, -top);
+                    C = scale2(C, -top);
+                    E += top;
+                }
+                const int sh = max(min(rE - E, 4000), -4000);
+                wM = scale2(rM, sh);
+                wI = scale2(rI, sh);
+                wP = scale2(rP, sh);
+            };
+            for (int i0 = 0; i0 < l && !dead; i0 += kWave) {
+                __syncthreads();
+                {
+                    const int i = i0 + lane;
+                    if (i < l) {
+                        const uint64_t a = roff + (uint64_t)i;
+                        rec[lane] = make_row_rec<R, SC>(b, t.p64, a, i, l);
+                        rinfo[lane] = read_base_index(b.reads[a]) | ((int)b.gq[a] << 16);
+                    }
+                }
+                __syncthreads();
+                const int nrows = l - i0 < kWave ? l - i0 : kWave;
+                if (has_prod) {
+                    // the window of records of rows i0 .. i0 + nrows - 1: one
+                    // round trip to L2 serves 64 rows, and the consumer trails
+                    // its producer by at least a window
+                    if (lane == 0) st_u32<__ATOMIC_RELAXED>(&ss.prog[pslot], (uint32_t)i0);
+                    uint32_t spins = 0;
+                    R bM = (R)0, bI = (R)0, bP = (R)0, bE = (R)0;
+                    for (;;) {
+                        const int row = i0 + lane;
+                        const uint32_t par = ((uint32_t)row / kRing) & 1u;
+                        const R* rp = pring + (size_t)((uint32_t)row % kRing) * 4;
+                        bool ok = true;
+                        if (lane < nrows) {
+                            bM = ld_relaxed(rp + 0);
+                            bI = ld_relaxed(rp + 1);
+                            bP = ld_relaxed(rp + 2);
+                            bE = ld_relaxed(rp + 3);
+                            ok = parity_of(bM) == par && parity_of(bI) == par &&
+                                 parity_of(bP) == par && parity_of(bE) == par;
+                        }
+                        if (__ballot(!ok) == 0ull) break;
+                        if (++spins > spin_limit) { raise_timeout(w); dead = true; break; }
+                        if ((spins & 63u) == 0u && aborted(w)) { dead = true; break; }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    if (__ballot(dead) != 0ull) break;
+                    rE = (int)((double)magnitude(bE) - (double)LongGeom<R>::exp_bias);
+                    rM = magnitude(bM);
+                    rI = magnitude(bI);
+                    rP = magnitude(bP);
+                    const R mrec = maxR(rM, maxR(rI, rP));
+                    rTop = lane < nrows && mrec > (R)0 ? rE + exponent_of(mrec) : kNoRec;
+                }
+                int tt = 0;
+                // groups of kRescaleRows rows: ping-pong in pairs, rescale at the end
+                for (; tt + kRescaleRows <= nrows && !dead; tt += kRescaleRows) {
+                    if (has_prod) take_records(tt, kRescaleRows);
+#pragma unroll 1
+                    for (int q = 0; q < kRescaleRows; q += 2) {
+                        if (!do_row(i0 + tt + q, tt + q, Ma, Ia, Mb, Ib)) break;
+                        if (!do_row(i0 + tt + q + 1, tt + q + 1, Mb, Ib, Ma, Ia)) break;
+                    }
+                    if (dead) break;
+                    rescale(Ma, Ia);
+                }
+                // the last rows of the read
+                if (tt < nrows && !dead && has_prod) take_records(tt, nrows - tt);
+                for (; tt < nrows && !dead; tt += 2) {
+                    if (!do_row(i0 + tt, tt, Ma, Ia, Mb, Ib)) break;
+                    if (tt + 1 < nrows) {
+                        if (!do_row(i0 + tt + 1, tt + 1, Mb, Ib, Ma, Ia)) break;
+                    } else {
+#pragma unroll
+                        for (int n = 0; n < N; ++n) { Ma[n] = Mb[n]; Ia[n] = Ib[n]; }
+                    }
                 }
             }
-        }
+        };
+        if (sc_ok)
+            run_rows(std::true_type{});
+        else
+            run_rows(std::false_type{});
         if (__ballot(dead) != 0ull) break;
 
         // ---- eq.4 over this tile's real columns, then accumulate along the tiles
-        double sp = 0.0;
+        R sp = (R)0;
 #pragma unroll
         for (int n = 0; n < N; ++n)
             if (c0 + (uint32_t)n < k) sp += Ma[n] + Ia[n];
         sp = seg_scan(sp, ones);
-        double am = rd_lane(sp, 63);
-        long long aE = E;
+        double am = (double)rd_lane(sp, 63);
+        long long aE = (long long)E;
         if (has_prod) {
             uint32_t spins = 0;
             double fm = 0.0, fe = 0.0;
             for (;;) {
-                fm = ld_relaxed(pring + (size_t)kRing * 4 + 0);
-                fe = ld_relaxed(pring + (size_t)kRing * 4 + 1);
+                fm = ld_relaxed(pfin + 0);
+                fe = ld_relaxed(pfin + 1);
                 const bool ok = parity_of(fm) == 0u && parity_of(fe) == 0u;
                 if (__builtin_amdgcn_readfirstlane((int)ok)) break;
                 if (++spins > spin_limit) { raise_timeout(w); dead = true; break; }
@@ -505,15 +587,15 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
             if (dead) break;
             fm = rd_lane(fm, 0);
             fe = rd_lane(fe, 0);
-            acc_add(am, aE, magnitude(fm), (long long)(magnitude(fe) - kExpBias));
+            acc_add(am, aE, magnitude(fm), (long long)(magnitude(fe) - 1099511627776.0));
             // the producer's ring has been read completely
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             if (lane == 0) st_u32<__ATOMIC_RELEASE>(&ss.done[pslot], it);
         }
         if (has_cons) {
             if (lane == 0) {
-                st_relaxed(ring + (size_t)kRing * 4 + 0, with_parity(am, 0u));
-                st_relaxed(ring + (size_t)kRing * 4 + 1, with_parity((double)aE + kExpBias, 0u));
+                st_relaxed(fin + 0, with_parity(am, 0u));
+                st_relaxed(fin + 1, with_parity((double)aE + 1099511627776.0, 0u));
             }
         } else if (lane == 0) {
             double out;
@@ -525,18 +607,29 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
                 out = -__builtin_inf();
             }
             b.out[pair] = out;
-            if (b.flags) b.flags[pair] = 0x04 | 0x08 | 0x10;  // long, rescaled, FP64
+            // long, rescaled, and the precision
+            if (b.flags) b.flags[pair] = (uint8_t)(0x04 | 0x08 | (sizeof(R) == 4 ? 0x01 : 0x10));
         }
     }
 }
 
-void launch_long(hipStream_t s, int grid, const Batch& b, const Tables& t, const Work& w,
+void launch_long(hipStream_t s, const int (&grid)[2], const Batch& b, const Tables& t, const Work& w,
                  const Policy& p)
 {
-    hipLaunchKernelGGL(long_prefix_kernel, dim3(1), dim3(256), 0, s, b, w, long_slots(grid));
-    hipLaunchKernelGGL(long_kernel, dim3(grid), dim3(kWave), 0, s, b, t, w, p);
+    hipLaunchKernelGGL(long_prefix_kernel, dim3(1), dim3(256), 0, s, b, w, long_slots(grid[0]), 0,
+                       long_tile_cols(true));
+    hipLaunchKernelGGL(long_kernel<float>, dim3(grid[0]), dim3(kWave), 0, s, b, t, w, p);
+    hipLaunchKernelGGL(long_prefix_kernel, dim3(1), dim3(256), 0, s, b, w, long_slots(grid[1]), 1,
+                       long_tile_cols(false));
+    hipLaunchKernelGGL(long_kernel<double>, dim3(grid[1]), dim3(kWave), 0, s, b, t, w, p);
 }
 
-const void* long_kernel_ptr() { return reinterpret_cast<const void*>(&long_kernel); }
+const void* long_kernel_ptr(bool fp32)
+{
+    return fp32 ? reinterpret_cast<const void*>(&long_kernel<float>)
+                : reinterpret_cast<const void*>(&long_kernel<double>);
+}
+
+size_t long_ring_slot_bytes() { return kRingSlotBytes; }
 
 }  // namespace phmm

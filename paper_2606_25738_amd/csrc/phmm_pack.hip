@@ -84,6 +84,7 @@ __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w,
         const uint32_t r = b.pairs[2 * p];
         const uint32_t l = (uint32_t)(b.read_off[r + 1] - b.read_off[r]);
         const int prec = (pol.precision == 1 || l > pol.fp32_max_rows) ? 1 : 0;
+        const int lprec = (pol.precision == 1 || l > pol.long_fp32_max_rows) ? 1 : 0;
         Greedy g[kNumClasses];
         bool fits[kNumClasses];
 #pragma unroll
@@ -95,8 +96,8 @@ __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w,
         for (uint64_t q = p; q < e; ++q) {
             const uint32_t k = hap_len(b, b.pairs[2 * q + 1]);
             if (k > kShortMaxCols) {
-                const uint32_t idx = atomicAdd(&w.ctr->n_long, 1u);
-                w.long_list[idx] = (uint32_t)q;
+                const uint32_t idx = atomicAdd(&w.ctr->n_long[lprec], 1u);
+                w.long_list[lprec][idx] = (uint32_t)q;
 #pragma unroll
                 for (int c = 0; c < kNumClasses; ++c) {
                     g[c].used = kWave;

@@ -255,6 +255,45 @@ def test_long_pairs_multi_tile(ctx32):
     check(b, out, fl)
 
 
+def test_long_pairs_fp32_within_row_limit(ctx32):
+    """Long pairs with reads up to the FP32 row limit (4096) run in the FP32
+    long kernel with rescaling; longer reads run in FP64."""
+    rng = np.random.default_rng(21)
+    pairs = []
+    for l in (1000, 2500, 4096, 4097):
+        hap = rnd(rng, max(int(l * 1.1), 1700))  # longer than one short wavefront
+        read = bytearray(hap[20:20 + l])
+        for j in rng.integers(0, l, l // 50):
+            read[j] = ord("ACGT"[int(rng.integers(0, 4))])
+        pairs.append((bytes(read), hap, rng.integers(5, 31, l), 30, 30, 10))
+    b = make_batch(pairs)
+    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    assert np.all(fl & phmm.PHMM_FLAG_LONG) and np.all(fl & phmm.PHMM_FLAG_RESCALED)
+    assert np.all(fl[:3] & phmm.PHMM_FLAG_FP32) and (fl[3] & phmm.PHMM_FLAG_FP64)
+    want, d = check(b, out, fl)
+    say("FP32 long errors:", d[:3])
+
+
+def test_long_pairs_band_crosses_tiles_low_gap_penalty(ctx32, ctx64):
+    """The alignment band crosses every tile boundary, with a small gap
+    continuation penalty (T_DD near 1), so deletions that open at a tile's
+    first column carry weight across the tile: both precisions."""
+    rng = np.random.default_rng(33)
+    pairs = []
+    for l, gcp in ((3000, 2), (2200, 1)):
+        hap = rnd(rng, l + 300)
+        read = bytearray(hap[150:150 + l])
+        for j in rng.integers(0, l, l // 40):
+            read[j] = ord("ACGT"[int(rng.integers(0, 4))])
+        pairs.append((bytes(read), hap, rng.integers(10, 41, l), 40, 40, gcp))
+    b = make_batch(pairs)
+    for ctx in (ctx32, ctx64):
+        out, fl = phmm.phmm_forward_batch(ctx, b)
+        assert np.all(fl & phmm.PHMM_FLAG_LONG)
+        want, d = check(b, out, fl)
+        say("band-crossing long pairs: flags %s, errors %s" % (list(fl), d))
+
+
 def test_fp64_underflow_goes_to_rescaled_kernel(ctx64):
     """A short pair whose FP64 scaled sum underflows (log10 L < -597) is
     recomputed by the rescaling kernel."""
@@ -319,3 +358,34 @@ def test_copy_calibration_kernel():
     assert torch.equal(src, dst)
     with pytest.raises(phmm.PhmmError):
         phmm.phmm_copy_calib(src[:17], dst[:17])  # not a multiple of 16
+
+
+def test_autotune_costs_and_results():
+    with phmm.Context() as c:
+        default = c.class_costs()
+        assert np.allclose(default[0], [n + 3 for n in range(4, 25, 2)])
+        costs = c.autotune(seed=1)
+        say("tuned ns per wave-row FP32:", np.round(costs[0], 1), "FP64:", np.round(costs[1], 1))
+        assert np.all(costs > 0) and np.array_equal(costs, c.class_costs())
+        # a wavefront-row of 24 columns costs more than one of 4
+        assert costs[0][-1] > costs[0][0] and costs[1][-1] > costs[1][0]
+        b = synth.generate("cfg3", 7, 20)
+        out, fl = phmm.phmm_forward_batch(c, b)
+        n = len(out)
+        check(b, out, fl, np.arange(0, n, max(1, n // 400)))
+        # the table that runs a sample of the workload fastest: the measured
+        # one or N + a for one of the candidate offsets
+        import torch
+        sdb = phmm.DeviceBatch(b, "cuda:0")
+        ws = torch.empty(phmm.phmm_workspace_bytes(c, len(b["pair_list"]), sdb.max_read_len,
+                                                   sdb.max_hap_len), dtype=torch.uint8, device="cuda:0")
+        picked = c.autotune_sample(sdb, ws)
+        ns = np.arange(4, 25, 2)
+        fam = [np.allclose(picked[0], ns + a) for a in (0, 1, 2, 3, 5, 8, 12, 20)]
+        assert any(fam) or np.array_equal(picked, costs)
+        out2, fl2 = phmm.phmm_forward_batch(c, b)
+        check(b, out2, fl2, np.arange(0, n, max(1, n // 400)))
+        c.set_class_costs(default)
+        assert np.array_equal(c.class_costs(), default)
+        with pytest.raises(phmm.PhmmError):
+            c.set_class_costs(-default)
