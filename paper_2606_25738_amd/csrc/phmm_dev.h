@@ -18,11 +18,12 @@ enum : int {
 };
 
 // Lanes whose source is outside the pattern, or whose row is masked off,
-// read 0.
+// read 0 (bound_ctrl set: the move needs no zeroed destination when every
+// row is enabled).
 template <int CTRL, int ROWMASK = 0xf>
 __device__ __forceinline__ int dpp_i(int x)
 {
-    return __builtin_amdgcn_update_dpp(0, x, CTRL, ROWMASK, 0xf, false);
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, ROWMASK, 0xf, true);
 }
 template <int CTRL, int ROWMASK = 0xf>
 __device__ __forceinline__ float dpp(float x)
@@ -93,8 +94,7 @@ __device__ __forceinline__ ScanMul<R> make_sum_mul(int lane, int segstart)
     return m;
 }
 
-template <typename R>
-__device__ __forceinline__ R seg_scan(R x, const ScanMul<R>& m)
+__device__ __forceinline__ double seg_scan(double x, const ScanMul<double>& m)
 {
     x = fmaR(m.m1, dpp<kRowShr1>(x), x);
     x = fmaR(m.m2, dpp<kRowShr2>(x), x);
@@ -104,6 +104,34 @@ __device__ __forceinline__ R seg_scan(R x, const ScanMul<R>& m)
     x = fmaR(m.m31, dpp<kRowBcast31, 0xc>(x), x);
     return x;
 }
+
+// FP32: each step is one v_fmac_f32 whose first operand is read through the
+// DPP pattern, x += m * x[source lane]; a lane with no source reads 0
+// (bound_ctrl) and a lane of a disabled row is not written, so both keep x.
+// The leading s_nop gives the two wait states a DPP read needs after the VALU
+// write of its source; the trailing one covers a DPP read that follows.
+#define PHMM_SCAN_STEP(PAT, BC)                                                      \
+    asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 " PAT " bank_mask:0xf" BC   \
+                 : "+v"(x)                                                           \
+                 : "v"(mm))
+__device__ __forceinline__ float seg_scan(float x, const ScanMul<float>& m)
+{
+    float mm = m.m1;
+    PHMM_SCAN_STEP("row_shr:1 row_mask:0xf", " bound_ctrl:1");
+    mm = m.m2;
+    PHMM_SCAN_STEP("row_shr:2 row_mask:0xf", " bound_ctrl:1");
+    mm = m.m4;
+    PHMM_SCAN_STEP("row_shr:4 row_mask:0xf", " bound_ctrl:1");
+    mm = m.m8;
+    PHMM_SCAN_STEP("row_shr:8 row_mask:0xf", " bound_ctrl:1");
+    mm = m.m15;
+    PHMM_SCAN_STEP("row_bcast:15 row_mask:0xa", "");
+    mm = m.m31;
+    PHMM_SCAN_STEP("row_bcast:31 row_mask:0xc", "");
+    asm volatile("s_nop 1" ::: "memory");
+    return x;
+}
+#undef PHMM_SCAN_STEP
 
 // Emission select without compares.  Each haplotype column is an 8-bit
 // code with bit b set when a read base of index b matches it (A=0, C=1,

@@ -61,13 +61,17 @@ __device__ __forceinline__ const double* pow_table<double>(const Tables& t, int 
 
 constexpr int words_for(int n) { return (n + 3) / 4; }
 
-// Waves per SIMD the fast FP32 kernel of a class is compiled for: the
-// register budget of 4 waves (128 VGPRs) holds classes up to N = 14 without
-// spills, that of 3 waves (168) the wider ones.  Other kernels: no target.
+// Waves per SIMD the fast FP32 kernel of a class is compiled for (its
+// register budget is 512 / waves VGPRs).  Measured on the genome-scale batch
+// with every pair forced into one class: the most waves whose row loop keeps
+// all its values in registers wins (spills outside the row loop, once per
+// pack, cost nothing measurable); one wave more, with spills in the row loop,
+// loses 5-60%.  Other kernels: no target.
 template <typename R, int CLS, int KIND>
 constexpr int waves_target()
 {
-    return KIND != kFast32 ? 1 : CLS <= 5 ? 4 : 3;
+    constexpr int fast_waves[kNumClasses] = {7, 7, 6, 6, 6, 5, 5, 4, 4, 4, 4};
+    return KIND != kFast32 ? 1 : fast_waves[CLS];
 }
 
 // KIND kFast32 (R = float): walks the FP32 packs of class CLS; a pack whose
