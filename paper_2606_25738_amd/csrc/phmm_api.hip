@@ -376,7 +376,8 @@ extern "C" int phmm_last_counts(phmm_ctx* c, void* d_ws, phmm_counts* out)
         out->packs_fp32 += h.pack_cnt[0][k];
         out->packs_fp64 += h.pack_cnt[1][k];
     }
-    out->rerun_items = h.rerun_items;
+    out->rerun_items = 0;  // one item per FP32 pack with a rejected pair
+    for (int k = 0; k < kNumClasses; ++k) out->rerun_items += h.item_cnt[k];
     out->rerun_pairs = h.rerun_pairs;
     out->long_pairs = (uint64_t)h.n_long[0] + h.n_long[1];
     out->long_tiles = (uint64_t)h.long_tiles[0] + h.long_tiles[1];

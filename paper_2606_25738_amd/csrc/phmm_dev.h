@@ -279,9 +279,31 @@ __device__ __forceinline__ void row_step(const R (&Mi)[N], const R (&Ii)[N], R (
     Vp = V;
 }
 
+// The lane index, read afresh where it is called: values derived from it
+// inside a loop (LDS and global addresses) are then recomputed per iteration
+// with a few ALU instructions instead of being hoisted out of the loop and,
+// under register pressure, spilled to scratch memory.
+__device__ __forceinline__ int lane_here()
+{
+    int l;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+    return l;
+}
+
 __device__ __forceinline__ uint32_t wave_broadcast0(uint32_t x)
 {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
+// log10 of s * 2^(-scale_exp) for a positive normal float s (an FP32 result):
+// the mantissa's log2 from the hardware (v_log_f32, error well below 1e-7 on
+// [0.5, 1)) plus the exponent.  It needs no polynomial constants, which the
+// compiler would otherwise keep in registers across the whole pack.
+__device__ __forceinline__ double log10_scaled_f32(float s, int scale_exp)
+{
+    int e;
+    const float m = frexpf(s, &e);
+    return ((double)__builtin_amdgcn_logf(m) + (double)(e - scale_exp)) * 0.30102999566398119521;
 }
 
 // log10 of S * 2^(-scale_exp) with the exponent handled in integers.

@@ -66,8 +66,7 @@ struct Counters {
     uint32_t long_tiles[2];
     uint32_t long_cursor;
     uint32_t status;                     // 0 or a PHMM_E* code (as uint32)
-    uint32_t rerun_items;
-    uint32_t rerun_pairs;
+    uint32_t rerun_pairs;                // counted by the FP64 kernel
     unsigned long long lane_columns;
 };
 

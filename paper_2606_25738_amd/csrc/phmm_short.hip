@@ -64,13 +64,13 @@ constexpr int words_for(int n) { return (n + 3) / 4; }
 // Waves per SIMD the fast FP32 kernel of a class is compiled for (its
 // register budget is 512 / waves VGPRs).  Measured on the genome-scale batch
 // with every pair forced into one class: the most waves whose row loop keeps
-// all its values in registers wins (spills outside the row loop, once per
-// pack, cost nothing measurable); one wave more, with spills in the row loop,
-// loses 5-60%.  Other kernels: no target.
+// all its values in registers wins; spills outside the row loop (a few
+// values per pack, class 7 at 5 waves) cost less than the occupancy gains,
+// spills inside it cost 5-60%.  Other kernels: no target.
 template <typename R, int CLS, int KIND>
 constexpr int waves_target()
 {
-    constexpr int fast_waves[kNumClasses] = {7, 7, 6, 6, 6, 5, 5, 4, 4, 4, 4};
+    constexpr int fast_waves[kNumClasses] = {8, 7, 7, 6, 6, 6, 5, 5, 4, 4, 4};
     return KIND != kFast32 ? 1 : fast_waves[CLS];
 }
 
@@ -92,6 +92,11 @@ void short_kernel(Batch b, Tables t, Work w, Policy pol)
     __shared__ int rinfo[kWave];  // read-base class mask | gcp byte << 16
     __shared__ int sflag[kWave];
     __shared__ uint32_t srej;
+    // per pair (lane q < pairs of the pack): first lane | lanes << 8, pair
+    // index, bit in the pack mask; per lane: real columns; per lane: its sum
+    __shared__ uint32_t pinfo[3][kWave];
+    __shared__ int nrl[kWave];
+    __shared__ R psum[kWave];
 
     const int lane = (int)threadIdx.x;
     Counters* ctr = w.ctr;
@@ -107,6 +112,7 @@ void short_kernel(Batch b, Tables t, Work w, Policy pol)
         if (lane == 0) it = atomicAdd(cursor, 1u);
         it = wave_broadcast0(it);
         if (it >= count) break;
+        const int lane = lane_here();  // (one wavefront per workgroup)
 
         uint32_t pack_gi, mask;
         if (KIND == kFast32 || KIND == kGen32) {
@@ -127,6 +133,9 @@ void short_kernel(Batch b, Tables t, Work w, Policy pol)
         pack_gi = wave_broadcast0(pack_gi);
         mask = wave_broadcast0(mask);
         const bool rerun_item = !kFP32 && it >= n_plain;
+        // rerun pairs are counted where they are recomputed (a rare path), so
+        // the FP32 kernels touch only the per-class item counter per rejection
+        if (rerun_item && lane == 0) atomicAdd(&ctr->rerun_pairs, (uint32_t)__builtin_popcount(mask));
 
         // ---- read and its gap-continuation profile.  Scaled form possible:
         // T_IM > 0 (gap byte >= 1) and bounded insertion bytes on every row.
@@ -187,11 +196,15 @@ void short_kernel(Batch b, Tables t, Work w, Policy pol)
         const uint32_t hlo = (uint32_t)__shfl((int)(uint32_t)my_h, src);
         const uint32_t hhi = (uint32_t)__shfl((int)(uint32_t)(my_h >> 32), src);
         const uint64_t hoff = ((uint64_t)hhi << 32) | hlo;
-        const uint32_t pair = (uint32_t)__shfl((int)my_pair, src);
-        const uint32_t off = (uint32_t)__shfl((int)my_off, src);
-        const int seglanes = (int)((k + N - 1) / N);
         const int c0 = N * (lane - segstart);
-        const bool segend = real && (lane == segstart + seglanes - 1);
+        // what the result step needs after the rows goes to LDS now, so that
+        // none of it stays live in registers across the row loop
+        if (lane < nseg) {
+            pinfo[0][lane] = (uint32_t)my_start | ((uint32_t)s_lanes << 8);
+            pinfo[1][lane] = my_pair;
+            pinfo[2][lane] = my_off;
+        }
+        nrl[lane] = real ? max(0, min((int)k - c0, N)) : 0;
 
         // ---- haplotype columns as 8-bit match codes, four per register
         uint32_t hc[words_for(N)];
@@ -279,21 +292,32 @@ void short_kernel(Batch b, Tables t, Work w, Policy pol)
                 run_rows(std::false_type{});
         }
 
-        // ---- eq.4: S = sum_j M(l,j) + I(l,j) over the real columns
-        R s = (R)0;
+        // ---- eq.4: S = sum_j M(l,j) + I(l,j) over the real columns: each
+        // lane's partial sum, then one lane per pair adds its segment's lanes
+        // in lane order
+        {
+            const int nreal = nrl[lane];
+            R sl = (R)0;
 #pragma unroll
-        for (int n = 0; n < N; ++n)
-            if ((uint32_t)(c0 + n) < k) s += Ma[n] + Ia[n];
-        if (!real) s = (R)0;
-        s = seg_scan(s, make_sum_mul<R>(lane, segstart));
-
+            for (int n = 0; n < N; ++n)
+                if (n < nreal) sl += Ma[n] + Ia[n];
+            psum[lane] = sl;
+        }
+        __syncthreads();
         bool reject = false;
-        if (segend) {
+        uint32_t off = 0;
+        if (lane < nseg) {
+            const uint32_t pi = pinfo[0][lane];
+            const int first = (int)(pi & 0xffu), cnt = (int)(pi >> 8);
+            R s = (R)0;
+            for (int q = 0; q < cnt; ++q) s += psum[first + q];
+            const uint32_t pair = pinfo[1][lane];
+            off = pinfo[2][lane];
             const double S = (double)s;
             if (kFP32) {
                 reject = !(S >= (double)pol.accept_min_sum) || !(S < 3.0e38);
                 if (!reject) {
-                    b.out[pair] = log10_scaled(S, ScaleOf<R>::exp);
+                    b.out[pair] = log10_scaled_f32((float)s, ScaleOf<R>::exp);
                     if (b.flags) b.flags[pair] = 0x01;  // FP32 accepted
                 }
             } else {
@@ -318,8 +342,6 @@ void short_kernel(Batch b, Tables t, Work w, Policy pol)
                 const uint32_t idx = atomicAdd(&ctr->item_cnt[CLS], 1u);
                 w.items[ctr->item_base[CLS] + idx].pack = pack_gi;
                 w.items[ctr->item_base[CLS] + idx].mask = rm;
-                atomicAdd(&ctr->rerun_items, 1u);
-                atomicAdd(&ctr->rerun_pairs, (uint32_t)__builtin_popcount(rm));
             }
         }
     }
