@@ -95,10 +95,10 @@ typedef struct phmm_options {
                                rounding bias grows with the row count); default 2048 */
     uint32_t long_fp32_max_rows; /* long pairs (haplotype > 64 x 24) with reads up to
                                this many rows run in FP32 with rescaling, longer ones
-                               in FP64; default 4096.  The FP32 error grows with the
-                               row count (per-row coefficients are rounded once):
-                               measured 2.5e-4 in log10 at 32k rows, so about
-                               3e-5 at the default                                 */
+                               in FP64; default 32768.  The per-row coefficients are
+                               rounded to FP32 stochastically (unbiased, keyed by the
+                               row), which keeps the error within 1e-4 in log10 to
+                               about 32k rows (measured 1.3e-5 at 10k, 4.7e-5 at 32k). */
     uint32_t watchdog_spins;/* long kernel: polls of a neighbour tile before giving
                                up with PHMM_ETIMEOUT; 0 = default                     */
     int timing;             /* 1: record per-phase HIP events (phmm_last_timing)     */

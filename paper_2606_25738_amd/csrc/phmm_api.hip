@@ -72,7 +72,7 @@ extern "C" void phmm_default_options(phmm_options* o)
     o->force_class = -1;
     o->one_pair_per_wave = 0;
     o->fp32_max_rows = 2048;
-    o->long_fp32_max_rows = 4096;
+    o->long_fp32_max_rows = 32768;
     o->watchdog_spins = 0;
     o->timing = 0;
 }

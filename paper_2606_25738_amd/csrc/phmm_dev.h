@@ -196,7 +196,37 @@ struct RowRec {
 // s_r >= 2^-24 for every gap byte >= 1 (T_IM >= 1 - 10^-0.1), so the scaled
 // rows stay within 24 binary orders of the plain ones.
 
-template <typename R, bool SC>
+// FP64 coefficient to R.  DITHER (FP32 only): unbiased stochastic rounding
+// to one of the two floats around v, chosen by a hash of (row, coefficient).
+// Rounding every row's coefficients to nearest gives all rows with the same
+// quality bytes the same relative error, which adds up linearly over a long
+// read; dithered, the errors are uncorrelated from row to row and their sum
+// grows like the square root of the row count.  The hash depends only on the
+// row index, so every tile of a pair rounds identically.
+__device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x = (x ^ (x >> 16)) * 0x7feb352du;
+    x = (x ^ (x >> 15)) * 0x846ca68bu;
+    return x ^ (x >> 16);
+}
+template <typename R, bool DITHER>
+__device__ __forceinline__ R to_coef(double v, int i, int which)
+{
+    if constexpr (!DITHER || sizeof(R) != 4) {
+        return (R)v;
+    } else {
+        const float f = (float)v;
+        const double df = (double)f;
+        if (!(v > 0.0) || df == v || !(f < 3.0e38f)) return f;
+        const uint32_t u = __builtin_bit_cast(uint32_t, f);
+        const float lo = df > v ? __builtin_bit_cast(float, u - 1u) : f;  // v > 0: below is u - 1
+        const float hi = df > v ? f : __builtin_bit_cast(float, u + 1u);
+        const double r = (double)mix32((uint32_t)i * 8u + (uint32_t)which) * 2.3283064365386963e-10;
+        return r * ((double)hi - (double)lo) < v - (double)lo ? hi : lo;
+    }
+}
+
+template <typename R, bool SC, bool DITHER = false>
 __device__ __forceinline__ RowRec<R> make_row_rec(const Batch& B, const double* p64, uint64_t a,
                                                   int i, int l)
 {
@@ -215,21 +245,21 @@ __device__ __forceinline__ RowRec<R> make_row_rec(const Batch& B, const double* 
         const double tim2 = i + 2 < l ? 1.0 - p64[B.gq[a + 2]] : 1.0;  // T_IM_{i+2}
         const double s = i + 1 < l ? tim2 * p64[B.iq[a + 1]] : 1.0;    // s_i
         const double sp = tim1 * tmi;                                   // s_{i-1}
-        r.pm = (R)(s * pm);
-        r.px = (R)(s * px);
-        r.tmm = (R)(tmm / sp);
-        r.cd = (R)(cd / sp);
+        r.pm = to_coef<R, DITHER>(s * pm, i, 0);
+        r.px = to_coef<R, DITHER>(s * px, i, 1);
+        r.tmm = to_coef<R, DITHER>(tmm / sp, i, 2);
+        r.cd = to_coef<R, DITHER>(cd / sp, i, 3);
         r.a = (R)1;
-        r.b = (R)(tim1 * g / tim);
+        r.b = to_coef<R, DITHER>(tim1 * g / tim, i, 4);
     } else {
-        r.pm = (R)pm;
-        r.px = (R)px;
-        r.tmm = (R)tmm;
-        r.cd = (R)cd;
-        r.a = (R)tmi;
-        r.b = (R)g;
+        r.pm = to_coef<R, DITHER>(pm, i, 0);
+        r.px = to_coef<R, DITHER>(px, i, 1);
+        r.tmm = to_coef<R, DITHER>(tmm, i, 2);
+        r.cd = to_coef<R, DITHER>(cd, i, 3);
+        r.a = to_coef<R, DITHER>(tmi, i, 5);
+        r.b = to_coef<R, DITHER>(g, i, 4);
     }
-    r.tim = (R)tim;
+    r.tim = to_coef<R, DITHER>(tim, i, 6);
     r.pad = (R)0;
     return r;
 }

@@ -494,7 +494,7 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
                     const int i = i0 + lane;
                     if (i < l) {
                         const uint64_t a = roff + (uint64_t)i;
-                        rec[lane] = make_row_rec<R, SC>(b, t.p64, a, i, l);
+                        rec[lane] = make_row_rec<R, SC, true>(b, t.p64, a, i, l);
                         rinfo[lane] = read_base_index(b.reads[a]) | ((int)b.gq[a] << 16);
                     }
                 }

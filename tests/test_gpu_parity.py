@@ -255,9 +255,9 @@ def test_long_pairs_multi_tile(ctx32):
     check(b, out, fl)
 
 
-def test_long_pairs_fp32_within_row_limit(ctx32):
-    """Long pairs with reads up to the FP32 row limit (4096) run in the FP32
-    long kernel with rescaling; longer reads run in FP64."""
+def test_long_pairs_fp32_within_row_limit():
+    """Long pairs with reads up to the FP32 row limit (set to 4096 here) run in
+    the FP32 long kernel with rescaling; longer reads run in FP64."""
     rng = np.random.default_rng(21)
     pairs = []
     for l in (1000, 2500, 4096, 4097):
@@ -267,7 +267,8 @@ def test_long_pairs_fp32_within_row_limit(ctx32):
             read[j] = ord("ACGT"[int(rng.integers(0, 4))])
         pairs.append((bytes(read), hap, rng.integers(5, 31, l), 30, 30, 10))
     b = make_batch(pairs)
-    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    with phmm.Context(long_fp32_max_rows=4096) as c:
+        out, fl = phmm.phmm_forward_batch(c, b)
     assert np.all(fl & phmm.PHMM_FLAG_LONG) and np.all(fl & phmm.PHMM_FLAG_RESCALED)
     assert np.all(fl[:3] & phmm.PHMM_FLAG_FP32) and (fl[3] & phmm.PHMM_FLAG_FP64)
     want, d = check(b, out, fl)
@@ -304,6 +305,21 @@ def test_fp64_underflow_goes_to_rescaled_kernel(ctx64):
     want, d = check(b, out, fl, plain64=True)
     assert want[0] < -700
     assert fl[0] & phmm.PHMM_FLAG_RESCALED
+
+
+def test_long_fp32_beyond_default_row_limit():
+    """FP32 long pairs with dithered coefficient rounding, on reads of 10 and
+    32 kbp (above the default FP32 row limit): the error against the oracle
+    stays within the FP32 bound."""
+    b = synth.generate("cfg2", 0, 1)
+    b32 = synth.generate("cfg2", 32, 1)
+    with phmm.Context(long_fp32_max_rows=200000) as c:
+        for bb in (b, b32):
+            out, fl = phmm.phmm_forward_batch(c, bb)
+            assert fl[0] & phmm.PHMM_FLAG_FP32 and fl[0] & phmm.PHMM_FLAG_LONG
+            want, d = check(bb, out, fl)
+            say("FP32 long read %d: log10 L %.6f, oracle %.6f, error %.2e" %
+                (int(np.diff(bb["read_offsets"])[0]), out[0], want[0], d[0]))
 
 
 def test_cfg2_long_read_10k(ctx32):
