@@ -270,6 +270,53 @@ def time_steps(phmm, torch, ctx, db, out, fl, ws, stream, warmup, steps):
     return elapsed, avg
 
 
+SWEEP_LENGTHS = (32, 64, 128, 256, 512, 1024, 1536, 2048, 4096, 8192, 16384, 32768, 65536,
+                 131072)
+
+
+def sweep_leg(phmm, torch, args):
+    """Length sweep of equal-length pairs (read and haplotypes of L bases,
+    16 haplotypes per read), L = 32 ... 131072: kernel-only GCUPS (HIP events
+    around the whole pass, packer included) in the default FP32 + rerun mode
+    and in plain FP64, best of `--sweep-reps` passes after one warm-up."""
+    rows = []
+    for L in SWEEP_LENGTHS:
+        regions = max(1, min(1_000_000, int(math.ceil(args.sweep_cells / (16.0 * L * L)))))
+        b = synth.generate(synth.sweep_cfg(L, regions))
+        cells = int(pair_cells(b)[0].sum())
+        db = phmm.DeviceBatch(b, "cuda:0")
+        n = len(b["pair_list"])
+        out = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        fl = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+        res = {"length": L, "regions": regions, "pairs": n, "cells": cells}
+        for mode, prec, peak in (("fp32", phmm.PHMM_FP32_RERUN, FP32_PEAK_TFLOPS),
+                                 ("fp64", phmm.PHMM_FP64_PLAIN, FP32_PEAK_TFLOPS / 2)):
+            ctx = phmm.Context(precision=prec, timing=True)
+            ws = torch.empty(phmm.phmm_workspace_bytes(ctx, n, db.max_read_len, db.max_hap_len),
+                             dtype=torch.uint8, device="cuda:0")
+            stream = torch.cuda.Stream()
+            best = None
+            for r in range(1 + args.sweep_reps):
+                phmm.phmm_forward_batch_async(ctx, db, out, fl, ws, stream)
+                t = phmm.phmm_last_timing(ctx)["total_ms"]
+                if r > 0:
+                    best = t if best is None else min(best, t)
+            phmm.phmm_device_status(ctx, ws)
+            f = fl.cpu().numpy()
+            res[mode] = dict(ms=round(best, 3), gcups=round(cells / best / 1e6, 1),
+                             roofline_frac=round(FLOPS_PER_CELL * cells / (best / 1e3) / (peak * 1e12), 4),
+                             fp32_pairs=int(((f & 0x01) != 0).sum()), long_pairs=int(((f & 0x04) != 0).sum()),
+                             rerun_pairs=int(((f & 0x02) != 0).sum()))
+            ctx.close()
+            del ws
+        log("sweep L=%d: %d pairs, %.3g cells; FP32+rerun %.1f GCUPS (%.1f ms), FP64 %.1f GCUPS (%.1f ms)" %
+            (L, n, cells, res["fp32"]["gcups"], res["fp32"]["ms"], res["fp64"]["gcups"], res["fp64"]["ms"]))
+        rows.append(res)
+        del db, out, fl
+        torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,6 +342,12 @@ def main():
                     help="percent of CUs for the short lanes (0 = no CU masks)")
     ap.add_argument("--calib-copy-mib", type=int, default=1024,
                     help="size of the calibration copy run before the timed steps")
+    ap.add_argument("--sweep", action="store_true",
+                    help="run only the length sweep of equal-length pairs (32 .. 131072) and "
+                         "print its JSON line")
+    ap.add_argument("--sweep-cells", type=float, default=1e11,
+                    help="cells per length in the sweep (capped at 1,000,000 regions)")
+    ap.add_argument("--sweep-reps", type=int, default=3)
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic profile from two rocprofv3 --pmc runs (no GPU used)")
     ap.add_argument("--command", action="append", default=[],
@@ -308,6 +361,14 @@ def main():
         print("bench.py measures one GPU only; this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.sweep:
+        import torch
+        import paper_2606_25738_amd as phmm
+        rows = sweep_leg(phmm, torch, args)
+        print(json.dumps({"sweep": rows, "unit": "GCUPS (kernel-only)", "data": "synthetic",
+                          "workload": "equal-length pairs, 16 haplotypes per read"}))
+        return
 
     t = time.perf_counter()
     batch = synth.generate("cfg3", 0, args.regions)

@@ -320,6 +320,46 @@ __device__ __forceinline__ int lane_here()
     return l;
 }
 
+// ---------------------------------------------------------------- power-of-two scaling
+
+// Wavefront max of a non-negative int (0 = nothing).
+__device__ __forceinline__ int wave_max_int(int x)
+{
+    x = max(x, dpp_i<kRowShr1>(x));
+    x = max(x, dpp_i<kRowShr2>(x));
+    x = max(x, dpp_i<kRowShr4>(x));
+    x = max(x, dpp_i<kRowShr8>(x));
+    x = max(x, dpp_i<kRowBcast15, 0xa>(x));
+    x = max(x, dpp_i<kRowBcast31, 0xc>(x));
+    return __builtin_amdgcn_readlane(x, 63);
+}
+
+__device__ __forceinline__ float maxR(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ double maxR(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ int exponent_of(float v) { int e; frexpf(v, &e); return e; }
+__device__ __forceinline__ int exponent_of(double v) { int e; frexp(v, &e); return e; }
+__device__ __forceinline__ float scale2(float v, int e) { return ldexpf(v, e); }
+__device__ __forceinline__ double scale2(double v, int e) { return ldexp(v, e); }
+
+// 2^e as an exact R when it is a normal number of R (|e| within the exponent
+// range), so that scaling is one multiply; callers fall back to ldexp outside.
+template <typename R>
+__device__ __forceinline__ bool pow2_ok(int e)
+{
+    return sizeof(R) == 4 ? (e >= -126 && e <= 127) : (e >= -1022 && e <= 1023);
+}
+__device__ __forceinline__ float pow2f(int e) { return __builtin_bit_cast(float, (uint32_t)(e + 127) << 23); }
+__device__ __forceinline__ double pow2d(int e)
+{
+    return __builtin_bit_cast(double, (uint64_t)(e + 1023) << 52);
+}
+template <typename R>
+__device__ __forceinline__ R pow2(int e);
+template <>
+__device__ __forceinline__ float pow2<float>(int e) { return pow2f(e); }
+template <>
+__device__ __forceinline__ double pow2<double>(int e) { return pow2d(e); }
+
 __device__ __forceinline__ uint32_t wave_broadcast0(uint32_t x)
 {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);

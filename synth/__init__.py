@@ -117,6 +117,18 @@ _lock = threading.Lock()
 _lib = None
 
 
+def sweep_cfg(length: int, regions: int) -> dict:
+    """Equal-length pairs for the length sweep: per region one read of
+    `length` bases against 16 haplotypes of `length` bases (variants of one
+    source haplotype by 1-3 SNPs, so all keep the length); 1% substitutions,
+    0.1% indels of 1-3 bp in the read; base quality U{10..40}, ins/del 45,
+    gcp 10."""
+    return dict(_BASE, regions=regions, seed=5, n_haps_lo=16, n_haps_hi=16,
+                hap_len_lo=length, hap_len_hi=length, hap_mode=1, var_snp_frac=1.0,
+                reads_mode=0, reads_fixed=1, read_len_lo=length, read_len_hi=length)
+
+
+
 def build_synth(force: bool = True) -> str:
     os.makedirs(_BUILD, exist_ok=True)
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
