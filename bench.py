@@ -317,6 +317,49 @@ def sweep_leg(phmm, torch, args):
     return rows
 
 
+def small_batch_leg(phmm, torch, args):
+    """Latency of one small batch (about 3550 short pairs, all at once): the
+    whole pass on device-resident inputs (HIP events, packer included), and
+    the synchronous host-to-host call (inputs copied in, results copied
+    back), median and minimum over `--small-reps` calls after warm-up."""
+    b = synth.generate(synth.small_batch_cfg())
+    cells = int(pair_cells(b)[0].sum())
+    n = len(b["pair_list"])
+    db = phmm.DeviceBatch(b, "cuda:0")
+    out = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    fl = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    res = {"pairs": n, "cells": cells}
+    with phmm.Context(timing=True) as ctx:
+        ws = torch.empty(phmm.phmm_workspace_bytes(ctx, n, db.max_read_len, db.max_hap_len),
+                         dtype=torch.uint8, device="cuda:0")
+        stream = torch.cuda.Stream()
+        dev, phases = [], []
+        for r in range(5 + args.small_reps):
+            phmm.phmm_forward_batch_async(ctx, db, out, fl, ws, stream)
+            t = phmm.phmm_last_timing(ctx)
+            if r >= 5:
+                dev.append(t["total_ms"])
+                phases.append(t)
+        phmm.phmm_device_status(ctx, ws)
+        host, sync = [], []
+        for r in range(5 + args.small_reps):
+            t0 = time.perf_counter()
+            phmm.phmm_forward_batch(ctx, b)
+            if r >= 5:
+                host.append((time.perf_counter() - t0) * 1e3)
+                sync.append(phmm.phmm_last_timing(ctx)["total_ms"])
+    ph = {k: round(float(np.median([p[k] for p in phases])), 4) for k in phases[0]}
+    res.update(device_ms_median=round(float(np.median(dev)), 4), device_ms_min=round(min(dev), 4),
+               sync_pass_ms_median=round(float(np.median(sync)), 4),
+               host_to_host_ms_median=round(float(np.median(host)), 4),
+               host_to_host_ms_min=round(min(host), 4), phases_ms_median=ph)
+    log("small batch: %d pairs, %.3g cells: asynchronous pass %.3f ms (min %.3f), synchronising "
+        "pass %.3f ms, host-to-host %.3f ms; asynchronous phases %s"
+        % (n, cells, res["device_ms_median"], res["device_ms_min"], res["sync_pass_ms_median"],
+           res["host_to_host_ms_median"], ph))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,6 +391,9 @@ def main():
     ap.add_argument("--sweep-cells", type=float, default=1e11,
                     help="cells per length in the sweep (capped at 1,000,000 regions)")
     ap.add_argument("--sweep-reps", type=int, default=3)
+    ap.add_argument("--small-batch", action="store_true",
+                    help="run only the small-batch latency leg (about 3550 short pairs)")
+    ap.add_argument("--small-reps", type=int, default=50)
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic profile from two rocprofv3 --pmc runs (no GPU used)")
     ap.add_argument("--command", action="append", default=[],
@@ -362,6 +408,11 @@ def main():
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
+    if args.small_batch:
+        import torch
+        import paper_2606_25738_amd as phmm
+        print(json.dumps({"small_batch": small_batch_leg(phmm, torch, args), "data": "synthetic"}))
+        return
     if args.sweep:
         import torch
         import paper_2606_25738_amd as phmm

@@ -91,6 +91,8 @@ struct phmm_ctx {
     // synchronous-API arena
     void* arena = nullptr;
     size_t arena_bytes = 0;
+    // device counters read back by the synchronising pass (pinned)
+    Counters* h_ctr = nullptr;
     // timing
     hipEvent_t ev[6] = {};
     bool timed = false;
@@ -160,6 +162,7 @@ extern "C" void phmm_destroy(phmm_ctx* c)
     (void)hipFree(c->d_pw64);
     (void)hipFree(c->d_pw32);
     (void)hipFree(c->arena);
+    if (c->h_ctr) (void)hipHostFree(c->h_ctr);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -183,6 +186,7 @@ static int create_impl(phmm_ctx* c, int device)
         for (int cls = 0; cls < kNumClasses; ++cls)
             c->cost[prec][cls] = (float)class_n(cls) + 3.0f;  // row cost ~ N cells + scan
     HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->h_ctr), sizeof(Counters), hipHostMallocDefault));
     for (auto& e : c->ev) HIP_TRY(hipEventCreate(&e));
     for (int kind = 0; kind < kNumKernelKinds; ++kind)
         for (int cls = 0; cls < kNumClasses; ++cls) {
@@ -320,9 +324,76 @@ static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s)
     return PHMM_OK;
 }
 
-extern "C" int phmm_forward_batch_async(phmm_ctx* c, const phmm_device_batch* db, double* d_out,
-                                        uint8_t* d_flags, void* d_ws, size_t ws_bytes,
-                                        void* hip_stream)
+// The same pass for callers that wait for its end anyway (the synchronous API
+// and the serving lanes): the host reads the device counters after the packer
+// and after each kernel family, launches only the kernels that have work, and
+// gives each a grid no larger than its packs or items.  A persistent launch
+// with nothing to do still dispatches every workgroup of its grid (tens of
+// microseconds each), which dominates a small batch; the read-backs cost
+// about as much as one such launch each.
+static int enqueue_sync(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s)
+{
+    const Policy pol = make_policy(c->opt, c->cost);
+    Tables t;
+    t.p64 = c->d_p64;
+    t.pw64 = c->d_pw64;
+    t.pw32 = c->d_pw32;
+    const Work w = work_for(c, ws, b.n_pairs);
+    const bool timed = c->opt.timing != 0;
+    Counters* h = c->h_ctr;
+    auto fetch = [&]() -> int {
+        HIP_TRY(hipMemcpyAsync(h, w.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return PHMM_OK;
+    };
+    auto capped = [](int grid, uint64_t work) {
+        return (int)std::min<uint64_t>((uint64_t)grid, work);
+    };
+    int rc = PHMM_OK;
+    if (timed) HIP_TRY(hipEventRecord(c->ev[0], s));
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, s, w.ctr);
+    if (b.n_pairs > 0) launch_pack(s, b, w, pol);
+    if (timed) HIP_TRY(hipEventRecord(c->ev[1], s));
+    if (b.n_pairs > 0) {
+        if ((rc = fetch()) != PHMM_OK) return rc;
+        if (pol.precision == PHMM_FP32_RERUN) {
+            for (int cls = 0; cls < kNumClasses; ++cls)
+                if (h->pack_cnt[0][cls] > 0)
+                    launch_short(kFast32, cls, capped(c->grid_short[kFast32][cls], h->pack_cnt[0][cls]),
+                                 s, b, t, w, pol);
+            if ((rc = fetch()) != PHMM_OK) return rc;
+            bool deferred = false;
+            for (int cls = 0; cls < kNumClasses; ++cls)
+                if (h->defer_cnt[cls] > 0) {
+                    launch_short(kGen32, cls, capped(c->grid_short[kGen32][cls], h->defer_cnt[cls]), s,
+                                 b, t, w, pol);
+                    deferred = true;
+                }
+            if (deferred && (rc = fetch()) != PHMM_OK) return rc;
+        }
+        if (timed) HIP_TRY(hipEventRecord(c->ev[2], s));
+        for (int cls = 0; cls < kNumClasses; ++cls) {
+            const uint64_t n = (uint64_t)h->pack_cnt[1][cls] + h->item_cnt[cls];
+            if (n > 0) launch_short(kAll64, cls, capped(c->grid_short[kAll64][cls], n), s, b, t, w, pol);
+        }
+        if (timed) HIP_TRY(hipEventRecord(c->ev[3], s));
+        if ((rc = fetch()) != PHMM_OK) return rc;  // FP64 underflow adds long pairs
+        const int grid[2] = {h->n_long[0] > 0 ? c->grid_long[0] : 0,
+                             h->n_long[1] > 0 ? c->grid_long[1] : 0};
+        launch_long(s, grid, b, t, w, pol);
+    } else if (timed) {
+        HIP_TRY(hipEventRecord(c->ev[2], s));
+        HIP_TRY(hipEventRecord(c->ev[3], s));
+    }
+    if (timed) HIP_TRY(hipEventRecord(c->ev[4], s));
+    HIP_TRY(hipGetLastError());
+    c->timed = timed;
+    return PHMM_OK;
+}
+
+// Checks a device batch and fills the kernels' view of it.
+static int device_batch(phmm_ctx* c, const phmm_device_batch* db, double* d_out, uint8_t* d_flags,
+                        void* d_ws, size_t ws_bytes, Batch* b)
 {
     if (!c || !db) return fail(PHMM_EINVAL, "phmm_forward_batch_async: ctx or batch is NULL");
     if (db->n_pairs > 0xffffffffull) return fail(PHMM_ERANGE, "n_pairs exceeds 2^32-1");
@@ -336,21 +407,40 @@ extern "C" int phmm_forward_batch_async(phmm_ctx* c, const phmm_device_batch* db
         return fail(PHMM_ERANGE, "max_hap_len %u exceeds %u", db->max_hap_len, PHMM_MAX_HAP);
     const size_t need = phmm_workspace_bytes(c, db->n_pairs, db->max_read_len, db->max_hap_len);
     if (ws_bytes < need) return fail(PHMM_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
-    HIP_TRY(hipSetDevice(c->device));
+    b->reads = db->reads;
+    b->bq = db->base_quals;
+    b->iq = db->ins_quals;
+    b->dq = db->del_quals;
+    b->gq = db->gcp;
+    b->read_off = db->read_offsets;
+    b->haps = db->haplotypes;
+    b->hap_off = db->hap_offsets;
+    b->pairs = db->pair_list;
+    b->n_pairs = db->n_pairs;
+    b->out = d_out;
+    b->flags = d_flags;
+    return PHMM_OK;
+}
+
+extern "C" int phmm_forward_batch_async(phmm_ctx* c, const phmm_device_batch* db, double* d_out,
+                                        uint8_t* d_flags, void* d_ws, size_t ws_bytes,
+                                        void* hip_stream)
+{
     Batch b;
-    b.reads = db->reads;
-    b.bq = db->base_quals;
-    b.iq = db->ins_quals;
-    b.dq = db->del_quals;
-    b.gq = db->gcp;
-    b.read_off = db->read_offsets;
-    b.haps = db->haplotypes;
-    b.hap_off = db->hap_offsets;
-    b.pairs = db->pair_list;
-    b.n_pairs = db->n_pairs;
-    b.out = d_out;
-    b.flags = d_flags;
+    const int rc = device_batch(c, db, d_out, d_flags, d_ws, ws_bytes, &b);
+    if (rc != PHMM_OK) return rc;
+    HIP_TRY(hipSetDevice(c->device));
     return enqueue(c, b, d_ws, static_cast<hipStream_t>(hip_stream));
+}
+
+int phmm::forward_device_batch_sync(phmm_ctx* c, const phmm_device_batch* db, double* d_out,
+                              uint8_t* d_flags, void* d_ws, size_t ws_bytes, hipStream_t s)
+{
+    Batch b;
+    const int rc = device_batch(c, db, d_out, d_flags, d_ws, ws_bytes, &b);
+    if (rc != PHMM_OK) return rc;
+    HIP_TRY(hipSetDevice(c->device));
+    return enqueue_sync(c, b, d_ws, s);
 }
 
 extern "C" int phmm_device_status(phmm_ctx* c, void* d_ws)
@@ -525,7 +615,7 @@ extern "C" int phmm_forward_batch(phmm_ctx* c, const uint8_t* reads, const uint8
     b.n_pairs = n_pairs;
     b.out = reinterpret_cast<double*>(A + o_out);
     b.flags = reinterpret_cast<uint8_t*>(A + o_fl);
-    rc = enqueue(c, b, A + o_ws, s);
+    rc = enqueue_sync(c, b, A + o_ws, s);
     if (rc != PHMM_OK) return rc;
     Counters h;
     HIP_TRY(hipMemcpyAsync(&h, A + o_ws, sizeof h, hipMemcpyDeviceToHost, s));

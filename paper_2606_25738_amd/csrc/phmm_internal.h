@@ -112,6 +112,18 @@ struct Work {
 // Sets the calling thread's phmm_last_error() message; returns code.
 int set_error(int code, const char* msg);
 
+}  // namespace phmm
+struct phmm_ctx;
+struct phmm_device_batch;
+namespace phmm {
+
+// phmm_forward_batch_async's checks and work, launched as a synchronising pass:
+// the host reads the device counters between kernel families and launches
+// only kernels that have work.  Returns once the last kernels are enqueued;
+// the caller waits on the stream for them and for its own copies.
+int forward_device_batch_sync(phmm_ctx* c, const phmm_device_batch* db, double* d_out,
+                              uint8_t* d_flags, void* d_ws, size_t ws_bytes, hipStream_t s);
+
 struct Policy {
     int precision;          // 0 FP32+rerun, 1 FP64 plain
     int force_class;        // -1 or class index

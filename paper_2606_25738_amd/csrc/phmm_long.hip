@@ -575,15 +575,21 @@ __global__ __launch_bounds__(64) void long_kernel(Batch b, Tables t, Work w, Pol
     }
 }
 
+// Both lists in order (FP32, then FP64); a list whose grid is 0 is skipped
+// (the caller knows it is empty).
 void launch_long(hipStream_t s, const int (&grid)[2], const Batch& b, const Tables& t, const Work& w,
                  const Policy& p)
 {
-    hipLaunchKernelGGL(long_prefix_kernel, dim3(1), dim3(256), 0, s, b, w, long_slots(grid[0]), 0,
-                       long_tile_cols(true));
-    hipLaunchKernelGGL(long_kernel<float>, dim3(grid[0]), dim3(kWave), 0, s, b, t, w, p);
-    hipLaunchKernelGGL(long_prefix_kernel, dim3(1), dim3(256), 0, s, b, w, long_slots(grid[1]), 1,
-                       long_tile_cols(false));
-    hipLaunchKernelGGL(long_kernel<double>, dim3(grid[1]), dim3(kWave), 0, s, b, t, w, p);
+    if (grid[0] > 0) {
+        hipLaunchKernelGGL(long_prefix_kernel, dim3(1), dim3(256), 0, s, b, w, long_slots(grid[0]),
+                           0, long_tile_cols(true));
+        hipLaunchKernelGGL(long_kernel<float>, dim3(grid[0]), dim3(kWave), 0, s, b, t, w, p);
+    }
+    if (grid[1] > 0) {
+        hipLaunchKernelGGL(long_prefix_kernel, dim3(1), dim3(256), 0, s, b, w, long_slots(grid[1]),
+                           1, long_tile_cols(false));
+        hipLaunchKernelGGL(long_kernel<double>, dim3(grid[1]), dim3(kWave), 0, s, b, t, w, p);
+    }
 }
 
 const void* long_kernel_ptr(bool fp32)

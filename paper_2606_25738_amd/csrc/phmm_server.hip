@@ -208,9 +208,10 @@ void phmm_server::worker(Lane* lane, uint32_t lane_id)
         db.max_read_len = ml;
         db.max_hap_len = mk;
         if (rc == PHMM_OK)
-            rc = phmm_forward_batch_async(lane->ctx, &db, reinterpret_cast<double*>(D + L.out),
-                                          reinterpret_cast<uint8_t*>(D + L.fl), D + L.ws,
-                                          L.total - L.ws, lane->stream);
+            rc = phmm::forward_device_batch_sync(lane->ctx, &db,
+                                                 reinterpret_cast<double*>(D + L.out),
+                                                 reinterpret_cast<uint8_t*>(D + L.fl), D + L.ws,
+                                                 L.total - L.ws, lane->stream);
         // results and the device counters (they open the workspace) come back
         // in two stream-ordered copies; only this lane's stream is waited on
         if (rc == PHMM_OK &&

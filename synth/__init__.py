@@ -117,6 +117,16 @@ _lock = threading.Lock()
 _lib = None
 
 
+def small_batch_cfg() -> dict:
+    """A small latency batch shaped like the paper's short-read test set (about
+    3550 pairs of reads and haplotypes up to 263 bases): 71 regions of 10
+    reads (100-150 bp) against 5 variant haplotypes of 150-263 bp; error and
+    quality model as in the one-region workload."""
+    return dict(_BASE, regions=71, seed=6, n_haps_lo=5, n_haps_hi=5, hap_len_lo=150,
+                hap_len_hi=263, hap_mode=1, reads_mode=0, reads_fixed=10, read_len_lo=100,
+                read_len_hi=150)
+
+
 def sweep_cfg(length: int, regions: int) -> dict:
     """Equal-length pairs for the length sweep: per region one read of
     `length` bases against 16 haplotypes of `length` bases (variants of one
