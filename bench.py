@@ -40,7 +40,10 @@ _BATCH = None  # inherited by the oracle worker processes
 # WRITE_SIZE runs of this script (see summarize_traffic); valid only for the
 # kernel sources and workload it was taken on.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_short_fp32_wgs.md")
+COUNTERS_PROFILE = os.path.join(ROOT, "profiles", "valu_counters_short_fp32_wgs.md")
+TRACE_PROFILE = os.path.join(ROOT, "profiles", "short_kernels_wgs_1M_regions.md")
 CSRC = os.path.join(ROOT, "paper_2606_25738_amd", "csrc")
+N_CLASSES = 11               # column classes of the short kernels (N = 4, 6, ..., 24)
 
 
 def log(*a):
@@ -94,6 +97,28 @@ def _pmc_rows(path, counter):
         return [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
 
 
+def _step_dispatches(path):
+    """Counter values (summed over a dispatch's rows) of the FP32 short-kernel
+    launches of the last forward pass in a rocprofv3 counter CSV: the last 22
+    dispatches of `short_kernel<float, c, kind>` by dispatch id.  Earlier
+    dispatches (the pack-cost autotuning on a sample) are left out."""
+    by = {}
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            m = re.search(r"short_kernel<float, (\d+), (\d+)>", r["Kernel_Name"])
+            if not m:
+                continue
+            d = by.setdefault(int(r["Dispatch_Id"]), dict(
+                cls=int(m.group(1)), kind=int(m.group(2)),
+                ns=int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+            d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    ids = sorted(by)[-2 * N_CLASSES:]
+    if len(ids) != 2 * N_CLASSES:
+        raise SystemExit("%s: %d FP32 short-kernel dispatches, expected at least %d"
+                         % (path, len(ids), 2 * N_CLASSES))
+    return [by[i] for i in ids]
+
+
 def summarize_traffic(fetch_csv, write_csv, out_path, regions, calib_mib, commands):
     """Writes the traffic profile from two rocprofv3 --pmc runs (FETCH_SIZE,
     then WRITE_SIZE) of `bench.py --steps 1 --warmup 0 --fp64-steps 0 --no-cpu`.
@@ -109,10 +134,8 @@ def summarize_traffic(fetch_csv, write_csv, out_path, regions, calib_mib, comman
             raise SystemExit("no copy_calib_kernel dispatch in %s" % path)
         factor = calib_mib * 1024.0 / calib[-1]
         per = {}
-        for r in rows:
-            m = re.search(r"short_kernel<float, (\d+), \d+>", r["Kernel_Name"])
-            if m:
-                per[int(m.group(1))] = per.get(int(m.group(1)), 0.0) + float(r["Counter_Value"])
+        for d in _step_dispatches(path):
+            per[d["cls"]] = per.get(d["cls"], 0.0) + d[name]
         res[name] = dict(factor=factor, calib_kib=calib[-1], per_class=per)
     f, w = res["FETCH_SIZE"], res["WRITE_SIZE"]
     fetch_b = sum(f["per_class"].values()) * 1024.0 * f["factor"]
@@ -121,7 +144,9 @@ def summarize_traffic(fetch_csv, write_csv, out_path, regions, calib_mib, comman
              "Commands (repository root, one MI355X):", ""]
     lines += ["    " + c for c in commands]
     lines += ["", "Workload: %d regions, one step (22 launches of `short_kernel<float, c, kind>`: the fast"
-              " and the general FP32 kernel of each class; counts per class summed over both)." % regions,
+              " and the general FP32 kernel of each class; counts per class summed over both). Only the"
+              " launches of the last forward pass count (the pack-cost autotuning before it runs the"
+              " same kernels on a sample)." % regions,
               "Counters are KiB per dispatch. Scale factor = known bytes of the calibration copy",
               "(`copy_calib_kernel`, %d MiB read and %d MiB written) / the counter's reading for it." %
               (calib_mib, calib_mib), "",
@@ -137,6 +162,127 @@ def summarize_traffic(fetch_csv, write_csv, out_path, regions, calib_mib, comman
               "- fetch_bytes_per_step: %.6e" % fetch_b,
               "- write_bytes_per_step: %.6e" % write_b,
               "- traffic_bytes_per_step: %.6e" % (fetch_b + write_b),
+              "- sources_sha256: %s" % sources_digest(), ""]
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_MUL_F32",
+                 "SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_INT32", "SQ_INSTS_VALU_FLOPS_FP32",
+                 "SQ_INSTS_SALU", "SQ_BUSY_CU_CYCLES", "GRBM_GUI_ACTIVE")
+
+
+def summarize_counters(pmc_csv, bench_json, out_path, commands):
+    """Writes the instruction-count profile of the FP32 short kernels from one
+    rocprofv3 --pmc run with VALU_COUNTERS, using the cell count from the JSON
+    line the profiled bench.py run printed.  SQ counters are summed over all
+    shader engines; GRBM_GUI_ACTIVE over the 8 XCDs (so the clock is it / 8 /
+    the dispatch's duration); SQ_BUSY_CU_CYCLES reads as CU-cycles summed over
+    the CUs (it agrees with 256 CUs x that clock x the duration)."""
+    rec = None
+    with open(bench_json) as fh:
+        for line in fh:
+            if line.startswith("{"):
+                rec = json.loads(line)
+    if rec is None:
+        raise SystemExit("no JSON line in %s" % bench_json)
+    cells = int(rec["config"]["cells"])
+    rows = _step_dispatches(pmc_csv)
+    tot = {c: sum(d.get(c, 0.0) for d in rows) for c in VALU_COUNTERS}
+    ns = sum(d["ns"] for d in rows)
+    fast = [d for d in rows if d["kind"] == 0]
+    lines = ["# VALU instruction counts of the FP32 short-pair kernels, genome-scale WGS-like batch", "",
+             "Commands (repository root, one MI355X):", ""]
+    lines += ["    " + c for c in commands]
+    lines += ["", "Workload: %d regions, %d pairs, %.6g cells; one forward pass (22 launches of"
+              " `short_kernel<float, c, kind>`, kind 0 the fast and 1 the general FP32 kernel)."
+              % (rec["config"]["regions"], rec["config"]["pairs"], cells),
+              "SQ counters are wave-instructions summed over the shader engines; the clock is"
+              " GRBM_GUI_ACTIVE / 8 XCDs / the dispatch's duration (under counter collection);"
+              " VALU per CU-clock = SQ_INSTS_VALU / SQ_BUSY_CU_CYCLES.", "",
+              "| class c (N = 4 + 2c) | ms | VALU | FMA_F32 | MUL_F32 | ADD_F32 | INT32 | SALU |"
+              " VALU per CU-clock | clock GHz |",
+              "|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for d in fast:
+        lines.append("| %d | %.2f | %.4g | %.4g | %.4g | %.4g | %.4g | %.4g | %.3f | %.2f |" % (
+            d["cls"], d["ns"] / 1e6, d["SQ_INSTS_VALU"], d["SQ_INSTS_VALU_FMA_F32"],
+            d["SQ_INSTS_VALU_MUL_F32"], d["SQ_INSTS_VALU_ADD_F32"], d["SQ_INSTS_VALU_INT32"],
+            d["SQ_INSTS_SALU"], d["SQ_INSTS_VALU"] / max(1.0, d["SQ_BUSY_CU_CYCLES"]),
+            d["GRBM_GUI_ACTIVE"] / 8.0 / max(1, d["ns"])))
+    lane = 64.0 * tot["SQ_INSTS_VALU"] / cells
+    fp = 64.0 * (tot["SQ_INSTS_VALU_FMA_F32"] + tot["SQ_INSTS_VALU_MUL_F32"]
+                 + tot["SQ_INSTS_VALU_ADD_F32"]) / cells
+    lines += ["", "Per useful cell over the pass (padding lanes and per-row work included):", "",
+              "- valu_lane_instructions_per_cell: %.3f" % lane,
+              "- fp32_fma_mul_add_lane_instructions_per_cell: %.3f" % fp,
+              "- int32_lane_instructions_per_cell: %.3f" % (64.0 * tot["SQ_INSTS_VALU_INT32"] / cells),
+              "- counted_fp32_flops_per_cell: %.3f" % (tot["SQ_INSTS_VALU_FLOPS_FP32"] / cells),
+              "- algorithmic_flops_per_cell: %d" % FLOPS_PER_CELL,
+              "- valu_per_cu_clock: %.3f" % (tot["SQ_INSTS_VALU"] / max(1.0, tot["SQ_BUSY_CU_CYCLES"])),
+              "- clock_ghz: %.3f" % (tot["GRBM_GUI_ACTIVE"] / 8.0 / max(1, ns)),
+              "- pass_ms_under_counters: %.2f" % (ns / 1e6),
+              "- sources_sha256: %s" % sources_digest(), ""]
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+def summarize_trace(trace_csv, bench_json, out_path, commands):
+    """Writes the kernel-duration profile of the FP32 short kernels from a
+    rocprofv3 --kernel-trace run of bench.py: the forward passes on the whole
+    batch (each 22 consecutive launches of `short_kernel<float, c, kind>`; the
+    three with the largest total, i.e. not the autotuning passes on a
+    sample), beside the HIP-event figure the same run printed."""
+    rec = None
+    with open(bench_json) as fh:
+        for line in fh:
+            if line.startswith("{"):
+                rec = json.loads(line)
+    if rec is None:
+        raise SystemExit("no JSON line in %s" % bench_json)
+    with open(trace_csv, newline="") as fh:
+        rows = sorted(csv.DictReader(fh), key=lambda r: int(r["Start_Timestamp"]))
+    calls, cur = [], []
+    for r in rows:
+        m = re.search(r"short_kernel<float, \d+, \d+>", r["Kernel_Name"])
+        if not m:
+            continue
+        cur.append((m.group(0), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
+        if len(cur) == 2 * N_CLASSES:
+            calls.append(cur)
+            cur = []
+    n_big = rec["warmup"] + rec["steps"]
+    tot = [sum(d for _, d in c) for c in calls]
+    big = sorted(sorted(range(len(calls)), key=lambda i: -tot[i])[:n_big])
+    per = {}
+    for i in big:
+        for name, d in calls[i]:
+            a = per.setdefault(name, [0, 0.0])
+            a[0] += 1
+            a[1] += d
+    steps_ms = [tot[i] / 1e3 for i in big]
+    timed = steps_ms[rec["warmup"]:]
+    cfg = rec["config"]
+    lines = ["# Kernel durations of the FP32 short-pair kernels, genome-scale WGS-like batch", "",
+             "Commands (repository root, one MI355X):", ""]
+    lines += ["    " + c for c in commands]
+    lines += ["", "Workload: %d regions, %d pairs, %.6g cells. The run autotunes the pack costs on a"
+              " sample before its timed steps, so the table is taken from the kernel trace"
+              " (`run_kernel_trace.csv`): the %d forward calls on the whole batch (%d warm-up + %d"
+              " timed), each 22 launches of `short_kernel<float, c, kind>` (class c has N = 4 + 2c"
+              " columns per lane; kind 0 is the fast FP32 kernel, 1 the general one)."
+              % (cfg["regions"], cfg["pairs"], cfg["cells"], n_big, rec["warmup"], rec["steps"]), "",
+              "| kernel | calls | total us | average us |", "|---|---:|---:|---:|"]
+    for name, (c, d) in sorted(per.items(), key=lambda kv: -kv[1][1]):
+        lines.append("| %s | %d | %.1f | %.1f |" % (name, c, d, d / c))
+    lines += ["", "FP32 short-pair family per forward call (sum of its 22 launches): "
+              + ", ".join("%.1f ms" % x for x in steps_ms)
+              + "; mean of the timed calls %.1f ms." % (sum(timed) / len(timed)),
+              "HIP events on the launch stream in the same run (`roofline.kernel_ms`, mean of the"
+              " timed steps): %.1f ms." % rec["roofline"]["kernel_ms"], "",
+              "- trace_family_ms: %.3f" % (sum(timed) / len(timed)),
+              "- events_family_ms: %.3f" % rec["roofline"]["kernel_ms"],
               "- sources_sha256: %s" % sources_digest(), ""]
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines))
@@ -166,9 +312,9 @@ def serve_leg(phmm, args):
     """The served request stream: regions of the mixed workload (95% short,
     5% long-read regions) arrive Poisson at a fixed rate; the server batches
     them continuously.  First the sustainable capacity is measured by
-    submitting a block of regions at once, then the stream runs at
-    args.serve_load times that capacity for args.serve_seconds."""
-    import threading
+    submitting a block of regions at once, then one stream runs for
+    args.serve_seconds at each fraction of that capacity in args.serve_loads
+    (fresh regions for each stream)."""
     gen_chunk = 2000
     cache = {}
 
@@ -196,51 +342,68 @@ def serve_leg(phmm, args):
             % (n_cap, cap_cells, span, cap_rps, cap_cells / span / 1e9))
         del regs
         cache.clear()
-        # the stream (all its regions generated before the clock starts)
-        rate = args.serve_load * cap_rps
-        rng = np.random.default_rng(4)
-        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * args.serve_seconds * 1.2) + 10))
-        arrivals = arrivals[arrivals < args.serve_seconds]
-        n = len(arrivals)
-        regs = [region(n_cap + q) for q in range(n)]
-        tickets = [None] * n
-        late = [0.0]
-
-        def submitter():
-            base = time.perf_counter()
-            for q in range(n):
-                r = regs[q]
-                d = base + arrivals[q] - time.perf_counter()
-                if d > 0:
-                    time.sleep(d)
-                else:
-                    late[0] = max(late[0], -d)
-                tickets[q] = srv.submit(r)
-        th = threading.Thread(target=submitter)
-        ts0 = time.perf_counter()
-        th.start()
-        lat, lat_s, lat_l, cells = [], [], [], 0
-        for q in range(n):
-            while tickets[q] is None:
-                time.sleep(0.0002)
-            _, _, info = srv.wait(tickets[q])
-            lat.append(info["latency_s"])
-            (lat_l if info["is_long"] else lat_s).append(info["latency_s"])
-            cells += info["cells"]
-        th.join()
-        wall = time.perf_counter() - ts0
-        st = srv.stats()
-    res = dict(arrival="poisson", rate_regions_per_s=round(rate, 2), load=args.serve_load,
-               capacity_regions_per_s=round(cap_rps, 2),
-               capacity_gcups=round(cap_cells / span / 1e9, 2), seconds=args.serve_seconds,
-               regions=n, cells=cells, gcups=round(cells / wall / 1e9, 2),
-               latency_all=_percentiles(lat), latency_short=_percentiles(lat_s),
-               latency_long=_percentiles(lat_l), batches=int(st["batches"]),
-               full_batches=int(st["full_batches"]), max_submit_lag_ms=round(late[0] * 1e3, 3),
+        streams = []
+        first = n_cap
+        for si, load in enumerate(args.serve_loads):
+            streams.append(_serve_stream(srv, region, first, load, cap_rps, args.serve_seconds,
+                                         seed=4 + si))
+            first += streams[-1]["regions"]
+            cache.clear()
+    res = dict(arrival="poisson", capacity_regions_per_s=round(cap_rps, 2),
+               capacity_gcups=round(cap_cells / span / 1e9, 2), streams=streams,
                lanes=args.serve_lanes, long_lanes=1, short_cu_percent=args.serve_short_cu,
-               cu_mask_status=int(st["cu_mask_status"]), budget_gib=args.serve_budget_gib)
-    log("served stream: %d regions at %.1f/s, p50 %.2f ms, p99 %.2f ms, %.1f GCUPS"
-        % (n, rate, res["latency_all"]["p50_ms"], res["latency_all"]["p99_ms"], res["gcups"]))
+               budget_gib=args.serve_budget_gib)
+    return res
+
+
+def _serve_stream(srv, region, first, load, cap_rps, seconds, seed):
+    """One Poisson stream at load x capacity (all its regions generated
+    before the clock starts); latency percentiles over all, short and long
+    regions."""
+    import threading
+    rate = load * cap_rps
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * seconds * 1.2) + 10))
+    arrivals = arrivals[arrivals < seconds]
+    n = len(arrivals)
+    regs = [region(first + q) for q in range(n)]
+    tickets = [None] * n
+    late = [0.0]
+    st0 = srv.stats()
+
+    def submitter():
+        base = time.perf_counter()
+        for q in range(n):
+            r = regs[q]
+            d = base + arrivals[q] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            else:
+                late[0] = max(late[0], -d)
+            tickets[q] = srv.submit(r)
+    th = threading.Thread(target=submitter)
+    ts0 = time.perf_counter()
+    th.start()
+    lat, lat_s, lat_l, cells = [], [], [], 0
+    for q in range(n):
+        while tickets[q] is None:
+            time.sleep(0.0002)
+        _, _, info = srv.wait(tickets[q])
+        lat.append(info["latency_s"])
+        (lat_l if info["is_long"] else lat_s).append(info["latency_s"])
+        cells += info["cells"]
+    th.join()
+    wall = time.perf_counter() - ts0
+    st = srv.stats()
+    res = dict(load=load, rate_regions_per_s=round(rate, 2), seconds=seconds, regions=n,
+               cells=cells, gcups=round(cells / wall / 1e9, 2),
+               latency_all=_percentiles(lat), latency_short=_percentiles(lat_s),
+               latency_long=_percentiles(lat_l),
+               batches=int(st["batches"] - st0["batches"]),
+               full_batches=int(st["full_batches"] - st0["full_batches"]),
+               max_submit_lag_ms=round(late[0] * 1e3, 3), cu_mask_status=int(st["cu_mask_status"]))
+    log("served stream at %.1fx capacity: %d regions at %.1f/s, p50 %.2f ms, p99 %.2f ms, %.1f GCUPS"
+        % (load, n, rate, res["latency_all"]["p50_ms"], res["latency_all"]["p99_ms"], res["gcups"]))
     return res
 
 
@@ -317,6 +480,76 @@ def sweep_leg(phmm, torch, args):
     return rows
 
 
+def _best_pass(phmm, torch, ctx, db, reps):
+    """Best total of `reps` passes after one warm-up (HIP events), flags of the last."""
+    n = db.n_pairs
+    out = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    fl = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    ws = torch.empty(phmm.phmm_workspace_bytes(ctx, n, db.max_read_len, db.max_hap_len),
+                     dtype=torch.uint8, device="cuda:0")
+    stream = torch.cuda.Stream()
+    best = None
+    for r in range(1 + reps):
+        phmm.phmm_forward_batch_async(ctx, db, out, fl, ws, stream)
+        t = phmm.phmm_last_timing(ctx)["total_ms"]
+        if r > 0:
+            best = t if best is None else min(best, t)
+    phmm.phmm_device_status(ctx, ws)
+    return best, fl.cpu().numpy()
+
+
+def batched_uneven_leg(phmm, torch, args):
+    """The batched uneven short-pair workload (20,000 regions, 2-8 variant
+    haplotypes of 150-600 bp, 100-150 bp reads) and its stress variant with
+    i.i.d. haplotypes, in FP32 + rerun and in plain FP64: kernel-only GCUPS
+    and the share of pairs rerun in FP64."""
+    res = {}
+    for name, cfg in (("variant_haplotypes", "cfg1"), ("iid_haplotypes", synth.iid_haps_cfg("cfg1"))):
+        b = synth.generate(cfg)
+        cells = int(pair_cells(b)[0].sum())
+        db = phmm.DeviceBatch(b, "cuda:0")
+        r = {"pairs": db.n_pairs, "cells": cells}
+        for mode, prec in (("fp32_rerun", phmm.PHMM_FP32_RERUN), ("fp64", phmm.PHMM_FP64_PLAIN)):
+            with phmm.Context(precision=prec, timing=True) as ctx:
+                ms, f = _best_pass(phmm, torch, ctx, db, args.small_reps // 10 or 1)
+            r[mode] = dict(ms=round(ms, 3), gcups=round(cells / ms / 1e6, 1))
+            if prec == phmm.PHMM_FP32_RERUN:
+                r["rerun_fraction"] = round(float(((f & 0x02) != 0).mean()), 4)
+        r["speedup_fp32_rerun"] = round(r["fp64"]["ms"] / r["fp32_rerun"]["ms"], 3)
+        log("batched uneven pairs (%s): %d pairs, %.3g cells; FP32+rerun %.1f GCUPS (rerun %.1f%%), "
+            "FP64 %.1f GCUPS" % (name, r["pairs"], cells, r["fp32_rerun"]["gcups"],
+                                100 * r["rerun_fraction"], r["fp64"]["gcups"]))
+        res[name] = r
+        del db
+        torch.cuda.empty_cache()
+    return res
+
+
+def one_pair_per_wave_leg(phmm, torch, args, costs):
+    """FP64 on the first `args.opw_regions` regions of the genome-scale
+    workload in two forms: one pair per wavefront (no packing) and packed as
+    the FP64 path runs it, beside FP32 + rerun on the same pairs."""
+    b = synth.generate("cfg3", 0, args.opw_regions)
+    cells = int(pair_cells(b)[0].sum())
+    db = phmm.DeviceBatch(b, "cuda:0")
+    res = {"regions": args.opw_regions, "pairs": db.n_pairs, "cells": cells}
+    for name, kw in (("fp64_one_pair_per_wave", dict(precision=phmm.PHMM_FP64_PLAIN,
+                                                      one_pair_per_wave=True)),
+                     ("fp64_packed", dict(precision=phmm.PHMM_FP64_PLAIN)),
+                     ("fp32_rerun_packed", dict(precision=phmm.PHMM_FP32_RERUN))):
+        with phmm.Context(timing=True, **kw) as ctx:
+            if costs is not None:
+                ctx.set_class_costs(costs)
+            ms, _ = _best_pass(phmm, torch, ctx, db, 1)
+        res[name] = dict(ms=round(ms, 3), gcups=round(cells / ms / 1e6, 1))
+    log("FP64 one pair per wave %.1f GCUPS, FP64 packed %.1f, FP32+rerun packed %.1f (%d regions)"
+        % (res["fp64_one_pair_per_wave"]["gcups"], res["fp64_packed"]["gcups"],
+           res["fp32_rerun_packed"]["gcups"], args.opw_regions))
+    del db
+    torch.cuda.empty_cache()
+    return res
+
+
 def small_batch_leg(phmm, torch, args):
     """Latency of one small batch (about 3550 short pairs, all at once): the
     whole pass on device-resident inputs (HIP events, packer included), and
@@ -372,12 +605,21 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1,
                     help="timed steps of the plain FP64 path on the same batch (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--end-to-end", type=int, default=1,
+                    help="time the synchronous host-to-host call on the whole batch (0 = skip)")
+    ap.add_argument("--opw-regions", type=int, default=20000,
+                    help="regions for the FP64 one-pair-per-wave comparison (0 = skip)")
+    ap.add_argument("--uneven", type=int, default=1,
+                    help="run the batched uneven short-pair workload and its i.i.d. stress "
+                         "variant (0 = skip)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default pack cost model instead of measuring it")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the served Poisson stream (0 = no serving leg)")
-    ap.add_argument("--serve-load", type=float, default=0.8,
-                    help="arrival rate as a fraction of the measured serving capacity")
+    ap.add_argument("--serve-loads", type=lambda v: [float(x) for x in v.split(",")],
+                    default=[0.5, 0.8],
+                    help="arrival rates of the streams as fractions of the measured serving "
+                         "capacity (comma-separated)")
     ap.add_argument("--serve-capacity-regions", type=int, default=3000)
     ap.add_argument("--serve-lanes", type=int, default=3)
     ap.add_argument("--serve-budget-gib", type=int, default=24)
@@ -396,9 +638,23 @@ def main():
     ap.add_argument("--small-reps", type=int, default=50)
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic profile from two rocprofv3 --pmc runs (no GPU used)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("PMC_CSV", "BENCH_JSON"),
+                    help="write the VALU counter profile from a rocprofv3 --pmc run with "
+                         + " ".join(VALU_COUNTERS) + " and its bench.py output (no GPU used)")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_CSV", "BENCH_JSON"),
+                    help="write the kernel-duration profile from a rocprofv3 --kernel-trace run "
+                         "and its bench.py output (no GPU used)")
     ap.add_argument("--command", action="append", default=[],
                     help="with --summarize-traffic: a command line to record in the profile")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace[0], args.summarize_trace[1], TRACE_PROFILE,
+                        args.command)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters[0], args.summarize_counters[1], COUNTERS_PROFILE,
+                           args.command)
+        return
     if args.summarize_traffic:
         summarize_traffic(args.summarize_traffic[0], args.summarize_traffic[1], TRAFFIC_PROFILE,
                           args.regions, args.calib_copy_mib, args.command)
@@ -530,6 +786,27 @@ def main():
                     speedup_fp32_rerun=round(value / (cells / (e64 / args.fp64_steps) / 1e9), 3))
         ctx64.close()
 
+    end_to_end = None
+    if args.end_to_end:
+        # host arrays in, host results out (synchronous API): copies, device
+        # packing, kernels and read-back; the first call sizes the arena
+        with phmm.Context(timing=True) as hctx:
+            if costs is not None:
+                hctx.set_class_costs(costs)
+            walls = []
+            for r in range(2):
+                t = time.perf_counter()
+                phmm.phmm_forward_batch(hctx, batch)
+                walls.append(time.perf_counter() - t)
+                log("end-to-end call %d: %.2f s" % (r + 1, walls[-1]))
+        end_to_end = dict(seconds=round(walls[-1], 3), gcups=round(cells / walls[-1] / 1e9, 1),
+                          first_call_seconds=round(walls[0], 3),
+                          note="host numpy arrays (pageable) in, host log10 L and flags out; "
+                               "the second of two calls (the first also allocates the arena)")
+    del db, ws
+    torch.cuda.empty_cache()
+    opw = one_pair_per_wave_leg(phmm, torch, args, costs) if args.opw_regions > 0 else None
+    uneven = batched_uneven_leg(phmm, torch, args) if args.uneven else None
     serving = serve_leg(phmm, args) if args.serve_seconds > 0 else None
 
     parity = None
@@ -561,7 +838,8 @@ def main():
         lane_utilisation=round(cells32 / max(1, counts["lane_columns"] * 150), 4),
         pack_costs=None if costs is None else dict(fp32=np.round(costs[0], 3).tolist(),
                                                    fp64=np.round(costs[1], 3).tolist()),
-        fp64_plain=fp64, parity_sample=parity, serving=serving,
+        fp64_plain=fp64, fp64_one_pair_per_wave=opw, end_to_end=end_to_end,
+        batched_uneven=uneven, parity_sample=parity, serving=serving,
     )
     print(json.dumps(rec), flush=True)
 

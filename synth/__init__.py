@@ -117,6 +117,14 @@ _lock = threading.Lock()
 _lib = None
 
 
+def iid_haps_cfg(name: str = "cfg1") -> dict:
+    """The stress variant of a workload: the same recipe with every haplotype
+    drawn i.i.d. instead of as variants of one source haplotype, so that a
+    read matches one haplotype of its region and most of its pairs fall far
+    below FP32's range (and rerun in FP64)."""
+    return dict(CONFIGS[name], hap_mode=0)
+
+
 def small_batch_cfg() -> dict:
     """A small latency batch shaped like the paper's short-read test set (about
     3550 pairs of reads and haplotypes up to 263 bases): 71 regions of 10
