@@ -7,8 +7,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "phmm.h"
@@ -93,6 +95,10 @@ struct phmm_ctx {
     size_t arena_bytes = 0;
     // device counters read back by the synchronising pass (pinned)
     Counters* h_ctr = nullptr;
+    // chunked synchronous batches: copy stream, per-chunk events and counters
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t ev_chunk[16] = {};
+    Counters* h_chunk = nullptr;
     // timing
     hipEvent_t ev[6] = {};
     bool timed = false;
@@ -163,6 +169,11 @@ extern "C" void phmm_destroy(phmm_ctx* c)
     (void)hipFree(c->d_pw32);
     (void)hipFree(c->arena);
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+    if (c->copy_stream) (void)hipStreamSynchronize(c->copy_stream);
+    if (c->h_chunk) (void)hipHostFree(c->h_chunk);
+    for (auto& e : c->ev_chunk)
+        if (e) (void)hipEventDestroy(e);
+    if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -491,7 +502,77 @@ extern "C" int phmm_last_timing(phmm_ctx* c, phmm_timing* out)
 }
 
 // ---------------------------------------------------------------- validation
-static bool is_base(uint8_t x) { return x == 'A' || x == 'C' || x == 'G' || x == 'T' || x == 'N'; }
+// Host checks of a batch before any device work.  Large arrays are scanned in
+// parallel blocks (up to 16 threads, at least 16 Mi elements each); a scan
+// reports the first failing index of the whole array, so the error message is
+// the same as a sequential check's.
+
+template <typename F>  // bad(lo, hi): first failing index in [lo, hi), or hi
+static uint64_t first_failure(uint64_t n, F bad)
+{
+    const uint64_t kMinPerThread = 1ull << 24;
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const uint64_t nt = std::min<uint64_t>(std::min(16u, hw), std::max<uint64_t>(1, n / kMinPerThread));
+    if (nt <= 1) return bad(0, n);
+    std::vector<uint64_t> res(nt, n);
+    std::vector<std::thread> th;
+    const uint64_t per = (n + nt - 1) / nt;
+    for (uint64_t t = 0; t < nt; ++t) {
+        const uint64_t lo = std::min(n, per * t), hi = std::min(n, lo + per);
+        th.emplace_back([&res, &bad, t, lo, hi, n] {
+            const uint64_t f = bad(lo, hi);
+            res[t] = f < hi ? f : n;
+        });
+    }
+    for (auto& x : th) x.join();
+    return *std::min_element(res.begin(), res.end());
+}
+
+struct BaseTable {
+    uint8_t bad[256];
+    BaseTable()
+    {
+        for (int c = 0; c < 256; ++c)
+            bad[c] = !(c == 'A' || c == 'C' || c == 'G' || c == 'T' || c == 'N');
+    }
+};
+static const BaseTable kBases;
+
+// First byte in [lo, hi) that is not one of ACGTN (branch-free per block).
+static uint64_t first_non_base(const uint8_t* p, uint64_t lo, uint64_t hi)
+{
+    for (uint64_t i = lo; i < hi;) {
+        const uint64_t e = std::min(hi, i + 4096);
+        uint32_t acc = 0;
+        for (uint64_t j = i; j < e; ++j) acc |= kBases.bad[p[j]];
+        if (acc)
+            for (uint64_t j = i; j < e; ++j)
+                if (kBases.bad[p[j]]) return j;
+        i = e;
+    }
+    return hi;
+}
+
+// CSR offsets: first entry that is empty, not increasing or longer than
+// max_len (n when none), and the longest length before it.
+static uint64_t check_offsets(const uint64_t* off, uint64_t n, uint64_t max_len, uint32_t* longest)
+{
+    std::atomic<uint32_t> top{0};
+    const uint64_t f = first_failure(n, [&](uint64_t lo, uint64_t hi) {
+        uint32_t m = 0;
+        uint64_t i = lo;
+        for (; i < hi; ++i) {
+            if (off[i + 1] <= off[i] || off[i + 1] - off[i] > max_len) break;
+            m = std::max(m, (uint32_t)(off[i + 1] - off[i]));
+        }
+        uint32_t cur = top.load();
+        while (m > cur && !top.compare_exchange_weak(cur, m)) {
+        }
+        return i;
+    });
+    *longest = top.load();
+    return f;
+}
 
 static int validate(const uint8_t* reads, const uint8_t* bq, const uint8_t* iq, const uint8_t* dq,
                     const uint8_t* gq, const uint64_t* ro, uint32_t n_reads, const uint8_t* haps,
@@ -506,26 +587,31 @@ static int validate(const uint8_t* reads, const uint8_t* bq, const uint8_t* iq, 
     if (!reads || !bq || !iq || !dq || !gq || !haps) return fail(PHMM_EINVAL, "NULL sequence or quality array");
     if (ro[0] != 0) return fail(PHMM_EINVAL, "read_offsets[0] = %llu, must be 0", (unsigned long long)ro[0]);
     if (ho[0] != 0) return fail(PHMM_EINVAL, "hap_offsets[0] = %llu, must be 0", (unsigned long long)ho[0]);
-    for (uint32_t r = 0; r < n_reads; ++r) {
-        if (ro[r + 1] <= ro[r]) return fail(PHMM_EINVAL, "read %u is empty or offsets not increasing", r);
-        uint64_t len = ro[r + 1] - ro[r];
-        if (len > PHMM_MAX_READ) return fail(PHMM_ERANGE, "read %u has %llu bases (max %u)", r, (unsigned long long)len, PHMM_MAX_READ);
-        if (len > *max_l) *max_l = (uint32_t)len;
+    uint64_t r = check_offsets(ro, n_reads, PHMM_MAX_READ, max_l);
+    if (r < n_reads) {
+        if (ro[r + 1] <= ro[r]) return fail(PHMM_EINVAL, "read %llu is empty or offsets not increasing", (unsigned long long)r);
+        return fail(PHMM_ERANGE, "read %llu has %llu bases (max %u)", (unsigned long long)r,
+                    (unsigned long long)(ro[r + 1] - ro[r]), PHMM_MAX_READ);
     }
-    for (uint32_t h = 0; h < n_haps; ++h) {
-        if (ho[h + 1] <= ho[h]) return fail(PHMM_EINVAL, "haplotype %u is empty or offsets not increasing", h);
-        uint64_t len = ho[h + 1] - ho[h];
-        if (len > PHMM_MAX_HAP) return fail(PHMM_ERANGE, "haplotype %u has %llu bases (max %u)", h, (unsigned long long)len, PHMM_MAX_HAP);
-        if (len > *max_k) *max_k = (uint32_t)len;
+    uint64_t h = check_offsets(ho, n_haps, PHMM_MAX_HAP, max_k);
+    if (h < n_haps) {
+        if (ho[h + 1] <= ho[h]) return fail(PHMM_EINVAL, "haplotype %llu is empty or offsets not increasing", (unsigned long long)h);
+        return fail(PHMM_ERANGE, "haplotype %llu has %llu bases (max %u)", (unsigned long long)h,
+                    (unsigned long long)(ho[h + 1] - ho[h]), PHMM_MAX_HAP);
     }
     const uint64_t nb = ro[n_reads], nh = ho[n_haps];
-    for (uint64_t i = 0; i < nb; ++i)
-        if (!is_base(reads[i])) return fail(PHMM_EINVAL, "read base %llu is 0x%02x, not one of ACGTN", (unsigned long long)i, reads[i]);
-    for (uint64_t i = 0; i < nh; ++i)
-        if (!is_base(haps[i])) return fail(PHMM_EINVAL, "haplotype base %llu is 0x%02x, not one of ACGTN", (unsigned long long)i, haps[i]);
-    for (uint64_t p = 0; p < n_pairs; ++p) {
+    uint64_t i = first_failure(nb, [&](uint64_t lo, uint64_t hi) { return first_non_base(reads, lo, hi); });
+    if (i < nb) return fail(PHMM_EINVAL, "read base %llu is 0x%02x, not one of ACGTN", (unsigned long long)i, reads[i]);
+    i = first_failure(nh, [&](uint64_t lo, uint64_t hi) { return first_non_base(haps, lo, hi); });
+    if (i < nh) return fail(PHMM_EINVAL, "haplotype base %llu is 0x%02x, not one of ACGTN", (unsigned long long)i, haps[i]);
+    const uint64_t p = first_failure(n_pairs, [&](uint64_t lo, uint64_t hi) {
+        for (uint64_t q = lo; q < hi; ++q)
+            if (pl[2 * q] >= n_reads || pl[2 * q + 1] >= n_haps) return q;
+        return hi;
+    });
+    if (p < n_pairs) {
         if (pl[2 * p] >= n_reads) return fail(PHMM_EINVAL, "pair %llu: read index %u >= %u", (unsigned long long)p, pl[2 * p], n_reads);
-        if (pl[2 * p + 1] >= n_haps) return fail(PHMM_EINVAL, "pair %llu: haplotype index %u >= %u", (unsigned long long)p, pl[2 * p + 1], n_haps);
+        return fail(PHMM_EINVAL, "pair %llu: haplotype index %u >= %u", (unsigned long long)p, pl[2 * p + 1], n_haps);
     }
     return PHMM_OK;
 }
@@ -564,6 +650,39 @@ static int ensure_arena(phmm_ctx* c, size_t bytes)
     return PHMM_OK;
 }
 
+// Synchronous batches of at least 2 * kChunkPairs pairs move their inputs in
+// chunks of pairs (at most kMaxChunks) on a copy stream while the chunks
+// before them compute on the context's stream.
+constexpr uint64_t kChunkPairs = 1ull << 22;
+constexpr int kMaxChunks = 16;
+
+// Per chunk of pairs [p0[k], p0[k+1]): one past the largest read and
+// haplotype index any pair of chunks 0..k uses, so that chunk k can start
+// once those prefixes of the read and haplotype arrays are on the device.
+static void chunk_needs(const uint32_t* pl, const std::vector<uint64_t>& p0,
+                        std::vector<uint64_t>& need_r, std::vector<uint64_t>& need_h)
+{
+    const size_t nc = p0.size() - 1;
+    need_r.assign(nc, 0);
+    need_h.assign(nc, 0);
+    std::vector<std::thread> th;
+    for (size_t k = 0; k < nc; ++k)
+        th.emplace_back([&, k] {
+            uint64_t r = 0, h = 0;
+            for (uint64_t q = p0[k]; q < p0[k + 1]; ++q) {
+                r = std::max<uint64_t>(r, pl[2 * q] + 1ull);
+                h = std::max<uint64_t>(h, pl[2 * q + 1] + 1ull);
+            }
+            need_r[k] = r;
+            need_h[k] = h;
+        });
+    for (auto& x : th) x.join();
+    for (size_t k = 1; k < nc; ++k) {
+        need_r[k] = std::max(need_r[k], need_r[k - 1]);
+        need_h[k] = std::max(need_h[k], need_h[k - 1]);
+    }
+}
+
 extern "C" int phmm_forward_batch(phmm_ctx* c, const uint8_t* reads, const uint8_t* bq,
                                   const uint8_t* iq, const uint8_t* dq, const uint8_t* gq,
                                   const uint64_t* ro, uint32_t n_reads, const uint8_t* haps,
@@ -578,6 +697,11 @@ extern "C" int phmm_forward_batch(phmm_ctx* c, const uint8_t* reads, const uint8
     if (rc != PHMM_OK || n_pairs == 0) return rc;
     HIP_TRY(hipSetDevice(c->device));
     const uint64_t nb = ro[n_reads], nh = ho[n_haps];
+    const int nchunk = (int)std::min<uint64_t>(kMaxChunks, std::max<uint64_t>(1, n_pairs / kChunkPairs / 2));
+    std::vector<uint64_t> p0(nchunk + 1);
+    for (int k = 0; k <= nchunk; ++k) p0[k] = n_pairs * (uint64_t)k / (uint64_t)nchunk;
+    uint64_t chunk_max = 0;
+    for (int k = 0; k < nchunk; ++k) chunk_max = std::max(chunk_max, p0[k + 1] - p0[k]);
     size_t o = 0;
     const size_t o_reads = o; o = align256(o + nb * 5);
     const size_t o_ro = o; o = align256(o + ((size_t)n_reads + 1) * 8);
@@ -587,21 +711,12 @@ extern "C" int phmm_forward_batch(phmm_ctx* c, const uint8_t* reads, const uint8
     const size_t o_out = o; o = align256(o + n_pairs * 8);
     const size_t o_fl = o; o = align256(o + n_pairs);
     const size_t o_ws = o;
-    const size_t ws = phmm_workspace_bytes(c, n_pairs, max_l, max_k);
+    const size_t ws = phmm_workspace_bytes(c, chunk_max, max_l, max_k);
     o += ws;
     rc = ensure_arena(c, o);
     if (rc != PHMM_OK) return rc;
     char* A = static_cast<char*>(c->arena);
     hipStream_t s = c->stream;
-    HIP_TRY(hipMemcpyAsync(A + o_reads, reads, nb, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(A + o_reads + nb, bq, nb, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(A + o_reads + 2 * nb, iq, nb, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(A + o_reads + 3 * nb, dq, nb, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(A + o_reads + 4 * nb, gq, nb, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(A + o_ro, ro, ((size_t)n_reads + 1) * 8, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(A + o_haps, haps, nh, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(A + o_ho, ho, ((size_t)n_haps + 1) * 8, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(A + o_pl, pl, n_pairs * 8, hipMemcpyHostToDevice, s));
     Batch b;
     b.reads = reinterpret_cast<const uint8_t*>(A + o_reads);
     b.bq = b.reads + nb;
@@ -615,14 +730,76 @@ extern "C" int phmm_forward_batch(phmm_ctx* c, const uint8_t* reads, const uint8
     b.n_pairs = n_pairs;
     b.out = reinterpret_cast<double*>(A + o_out);
     b.flags = reinterpret_cast<uint8_t*>(A + o_fl);
-    rc = enqueue_sync(c, b, A + o_ws, s);
-    if (rc != PHMM_OK) return rc;
-    Counters h;
-    HIP_TRY(hipMemcpyAsync(&h, A + o_ws, sizeof h, hipMemcpyDeviceToHost, s));
+    // the byte ranges [b0, b1) of the five read arrays, of the haplotypes and
+    // of the pair list, on stream cs
+    auto copy_reads = [&](uint64_t b0, uint64_t b1, hipStream_t cs) -> int {
+        if (b1 <= b0) return PHMM_OK;
+        const uint8_t* src[5] = {reads, bq, iq, dq, gq};
+        for (int q = 0; q < 5; ++q)
+            HIP_TRY(hipMemcpyAsync(A + o_reads + q * nb + b0, src[q] + b0, b1 - b0,
+                                   hipMemcpyHostToDevice, cs));
+        return PHMM_OK;
+    };
+    auto copy_haps = [&](uint64_t b0, uint64_t b1, hipStream_t cs) -> int {
+        if (b1 > b0) HIP_TRY(hipMemcpyAsync(A + o_haps + b0, haps + b0, b1 - b0, hipMemcpyHostToDevice, cs));
+        return PHMM_OK;
+    };
+    auto copy_pairs = [&](uint64_t q0, uint64_t q1, hipStream_t cs) -> int {
+        if (q1 > q0)
+            HIP_TRY(hipMemcpyAsync(A + o_pl + q0 * 8, pl + 2 * q0, (q1 - q0) * 8, hipMemcpyHostToDevice, cs));
+        return PHMM_OK;
+    };
+    if (nchunk == 1) {
+        if ((rc = copy_reads(0, nb, s)) != PHMM_OK || (rc = copy_haps(0, nh, s)) != PHMM_OK ||
+            (rc = copy_pairs(0, n_pairs, s)) != PHMM_OK)
+            return rc;
+        HIP_TRY(hipMemcpyAsync(A + o_ro, ro, ((size_t)n_reads + 1) * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(A + o_ho, ho, ((size_t)n_haps + 1) * 8, hipMemcpyHostToDevice, s));
+        rc = enqueue_sync(c, b, A + o_ws, s);
+        if (rc != PHMM_OK) return rc;
+        HIP_TRY(hipMemcpyAsync(c->h_ctr, A + o_ws, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    } else {
+        // copies of chunk k+1 (pageable host memory: the host thread stages
+        // them) overlap the pass over chunk k, which the context's stream
+        // starts once its inputs are on the device
+        if (!c->copy_stream) HIP_TRY(hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
+        if (!c->h_chunk)
+            HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->h_chunk), kMaxChunks * sizeof(Counters),
+                                  hipHostMallocDefault));
+        for (int k = 0; k < nchunk; ++k)
+            if (!c->ev_chunk[k]) HIP_TRY(hipEventCreateWithFlags(&c->ev_chunk[k], hipEventDisableTiming));
+        std::vector<uint64_t> need_r, need_h;
+        chunk_needs(pl, p0, need_r, need_h);
+        hipStream_t cs = c->copy_stream;
+        HIP_TRY(hipMemcpyAsync(A + o_ro, ro, ((size_t)n_reads + 1) * 8, hipMemcpyHostToDevice, cs));
+        HIP_TRY(hipMemcpyAsync(A + o_ho, ho, ((size_t)n_haps + 1) * 8, hipMemcpyHostToDevice, cs));
+        uint64_t done_r = 0, done_h = 0;
+        for (int k = 0; k < nchunk; ++k) {
+            if ((rc = copy_reads(ro[done_r], ro[need_r[k]], cs)) != PHMM_OK ||
+                (rc = copy_haps(ho[done_h], ho[need_h[k]], cs)) != PHMM_OK ||
+                (rc = copy_pairs(p0[k], p0[k + 1], cs)) != PHMM_OK)
+                return rc;
+            done_r = std::max(done_r, need_r[k]);
+            done_h = std::max(done_h, need_h[k]);
+            HIP_TRY(hipEventRecord(c->ev_chunk[k], cs));
+            HIP_TRY(hipStreamWaitEvent(s, c->ev_chunk[k], 0));
+            Batch bk = b;
+            bk.pairs = b.pairs + 2 * p0[k];
+            bk.n_pairs = p0[k + 1] - p0[k];
+            bk.out = b.out + p0[k];
+            bk.flags = b.flags + p0[k];
+            rc = enqueue(c, bk, A + o_ws, s);
+            if (rc != PHMM_OK) return rc;
+            HIP_TRY(hipMemcpyAsync(c->h_chunk + k, A + o_ws, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        }
+    }
     HIP_TRY(hipMemcpyAsync(out, b.out, n_pairs * 8, hipMemcpyDeviceToHost, s));
     if (flags) HIP_TRY(hipMemcpyAsync(flags, b.flags, n_pairs, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (h.status != 0) return fail((int)h.status, "device reported error %d", (int)h.status);
+    for (int k = 0; k < nchunk; ++k) {
+        const uint32_t st = nchunk == 1 ? c->h_ctr->status : c->h_chunk[k].status;
+        if (st != 0) return fail((int)st, "device reported error %d", (int)st);
+    }
     return PHMM_OK;
 }
 

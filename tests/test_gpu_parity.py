@@ -400,6 +400,40 @@ def test_async_matches_sync(ctx32):
     assert counts["packs_fp32"] > 0
 
 
+def test_chunked_sync_call_matches_async(ctx32):
+    """A synchronous call large enough to be split into chunks of pairs (its
+    inputs copied chunk by chunk while earlier chunks compute) gives the
+    stream-ordered call's results, and a sample spread over both chunks
+    matches the oracle."""
+    import torch
+    b = synth.generate("cfg3", 0, 50000)
+    n = len(b["pair_list"])
+    assert n >= 2 * 2 * (1 << 22), n  # two chunks at least
+    sync_out, sync_fl = phmm.phmm_forward_batch(ctx32, b)
+    db = phmm.DeviceBatch(b)
+    ws = torch.empty(phmm.phmm_workspace_bytes(ctx32, n, db.max_read_len, db.max_hap_len),
+                     dtype=torch.uint8, device="cuda:0")
+    out = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    fl = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    s = torch.cuda.Stream()
+    phmm.phmm_forward_batch_async(ctx32, db, out, fl, ws, s)
+    s.synchronize()
+    phmm.phmm_device_status(ctx32, ws)
+    a_out, a_fl = out.cpu().numpy(), fl.cpu().numpy()
+    # packing of a read's pairs can differ at a chunk boundary (another column
+    # class: another summation order), so values agree to rounding
+    both32 = ((sync_fl & a_fl) & phmm.PHMM_FLAG_FP32) != 0
+    assert (sync_fl == a_fl).mean() > 0.9999
+    assert np.max(np.abs(sync_out[both32] - a_out[both32])) <= 2 * TOL32
+    same64 = (sync_fl == a_fl) & ((sync_fl & phmm.PHMM_FLAG_FP32) == 0)
+    if same64.any():
+        assert np.max(np.abs(sync_out[same64] - a_out[same64])) <= 2 * TOL64
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([rng.integers(0, n, 150), np.arange(n // 2 - 25, n // 2 + 25)]))
+    check(b, sync_out, sync_fl, idx=idx)
+    say("chunked synchronous call: %d pairs, %d differing flags" % (n, int((sync_fl != a_fl).sum())))
+
+
 def test_vector_peak_calibration():
     fp32, fp64 = phmm.phmm_vector_peak(0)
     say("vector FMA peak: FP32 %.1f, FP64 %.1f TFLOP/s" % (fp32, fp64))
