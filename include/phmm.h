@@ -142,6 +142,13 @@ int phmm_class_n(int c);
  * out_log10 : n_pairs doubles, log10 P(read | hap);
  * out_flags : n_pairs bytes of PHMM_FLAG_* bits, or NULL.
  * n_pairs == 0 is valid and does nothing.
+ *
+ * The host reads the device's counters between kernel families and
+ * launches only kernels that have work.  A batch of 2^23 pairs or more is
+ * split into up to 16 chunks of consecutive pairs; the inputs a chunk needs
+ * are copied on a second stream while the chunks before it compute
+ * (phmm_last_timing then describes the last chunk's pass).  Inputs need not
+ * be pinned; the call returns when the results are in the host buffers.
  */
 int phmm_forward_batch(phmm_ctx* ctx,
                        const uint8_t* reads, const uint8_t* base_quals,
