@@ -717,10 +717,10 @@ def main():
     costs = None
     if not args.no_autotune:
         # per-class costs measured on a synthetic batch, then the table that
-        # runs a sample of this workload (its first 20,000 regions) fastest
+        # runs a sample of this workload (its first 50,000 regions) fastest
         t = time.perf_counter()
         ctx.autotune(seed=0)
-        ns = min(args.regions, 20000)
+        ns = min(args.regions, 50000)
         sb = synth.generate("cfg3", 0, ns)
         sdb = phmm.DeviceBatch(sb, "cuda:0")
         sws = torch.empty(phmm.phmm_workspace_bytes(ctx, len(sb["pair_list"]), sdb.max_read_len,

@@ -102,6 +102,15 @@ typedef struct phmm_options {
     uint32_t watchdog_spins;/* long kernel: polls of a neighbour tile before giving
                                up with PHMM_ETIMEOUT; 0 = default                     */
     int timing;             /* 1: record per-phase HIP events (phmm_last_timing)     */
+    int route_diverse_fp64; /* 1 (default): in PHMM_FP32_RERUN mode, a read whose
+                               haplotypes are mutually unrelated (the 4-mer sets of
+                               their first 32 bases: none of the run's next three
+                               haplotypes shares half of the first one's) runs in FP64
+                               directly.  Such a read can match at most one of its
+                               haplotypes well, so most of its pairs would fall below
+                               the FP32 threshold and be recomputed anyway; 0: every
+                               read starts in FP32.  Results are within the same
+                               bounds either way; only the work differs.              */
 } phmm_options;
 
 /* Fills *opt with the defaults above. */
@@ -268,9 +277,10 @@ int phmm_autotune(phmm_ctx* ctx, uint64_t seed, float* out_costs /* NULL ok */);
 /* Pack-shape tuning on the caller's own workload: times a sample batch (device
  * buffers as phmm_forward_batch_async, with its workspace and stream) under
  * the context's current cost table and under the family cost = N + a for
- * a in {0, 1, 2, 3, 5, 8, 12, 20}, and keeps the fastest table.  It runs the
- * sample 27 times; results written to the sample's outputs are discarded (a
- * scratch output buffer is allocated for the duration of the call). */
+ * a in {0, 1, 2, 3, 5, 8, 12, 20} (best of 4 passes after a warm-up each),
+ * and keeps the fastest table.  It runs the sample 45 times; results written
+ * to the sample's outputs are discarded (a scratch output buffer is allocated
+ * for the duration of the call). */
 int phmm_autotune_sample(phmm_ctx* ctx, const phmm_device_batch* sample, void* d_workspace,
                          size_t ws_bytes, void* hip_stream, float* out_costs /* NULL ok */);
 int phmm_set_class_costs(phmm_ctx* ctx, const float* costs);

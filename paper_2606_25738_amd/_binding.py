@@ -41,7 +41,7 @@ class _Options(ctypes.Structure):
                 ("force_class", ctypes.c_int), ("one_pair_per_wave", ctypes.c_int),
                 ("fp32_max_rows", ctypes.c_uint32), ("long_fp32_max_rows", ctypes.c_uint32),
                 ("watchdog_spins", ctypes.c_uint32),
-                ("timing", ctypes.c_int)]
+                ("timing", ctypes.c_int), ("route_diverse_fp64", ctypes.c_int)]
 
 
 class _DeviceBatch(ctypes.Structure):
@@ -191,7 +191,8 @@ class Context:
                  accept_min_sum: float | None = None, force_class: int = -1,
                  one_pair_per_wave: bool = False, fp32_max_rows: int | None = None,
                  long_fp32_max_rows: int | None = None,
-                 watchdog_spins: int = 0, timing: bool = False):
+                 watchdog_spins: int = 0, timing: bool = False,
+                 route_diverse_fp64: bool = True):
         L = lib()
         o = _Options()
         L.phmm_default_options(ctypes.byref(o))
@@ -206,6 +207,7 @@ class Context:
             o.long_fp32_max_rows = long_fp32_max_rows
         o.watchdog_spins = watchdog_spins
         o.timing = int(bool(timing))
+        o.route_diverse_fp64 = int(bool(route_diverse_fp64))
         h = ctypes.c_void_p()
         _check(L.phmm_create(ctypes.byref(h), device, ctypes.byref(o)))
         self._h = h

@@ -77,6 +77,7 @@ extern "C" void phmm_default_options(phmm_options* o)
     o->long_fp32_max_rows = 32768;
     o->watchdog_spins = 0;
     o->timing = 0;
+    o->route_diverse_fp64 = 1;
 }
 
 // ---------------------------------------------------------------- context
@@ -118,6 +119,7 @@ static Policy make_policy(const phmm_options& o, const float (&cost)[2][kNumClas
     p.long_fp32_max_rows = o.long_fp32_max_rows;
     p.accept_min_sum = (float)o.accept_min_sum;
     p.watchdog_spins = o.watchdog_spins ? o.watchdog_spins : 4000000u;
+    p.route_diverse = o.route_diverse_fp64;
     for (int prec = 0; prec < 2; ++prec)
         for (int c = 0; c < kNumClasses; ++c) p.cost[prec][c] = cost[prec][c];
     return p;
@@ -131,6 +133,8 @@ static int check_options(const phmm_options& o)
         return fail(PHMM_EINVAL, "options.accept_min_sum must be in (0, 1e30]");
     if (o.force_class < -1 || o.force_class >= kNumClasses)
         return fail(PHMM_EINVAL, "options.force_class must be -1 or 0..%d", kNumClasses - 1);
+    if (o.route_diverse_fp64 != 0 && o.route_diverse_fp64 != 1)
+        return fail(PHMM_EINVAL, "options.route_diverse_fp64 must be 0 or 1");
     return PHMM_OK;
 }
 
@@ -906,7 +910,7 @@ extern "C" int phmm_autotune(phmm_ctx* c, uint64_t seed, float* out_costs)
             c->opt.one_pair_per_wave = 1;
             c->opt.timing = 1;
             float best = 0.f;
-            for (int rep = 0; rep < 3 && rc == PHMM_OK; ++rep) {  // first run warms up
+            for (int rep = 0; rep < 5 && rc == PHMM_OK; ++rep) {  // best of 4 after a warm-up  // first run warms up
                 rc = phmm_forward_batch(c, reads.data(), bq.data(), iq.data(), dq.data(), gq.data(),
                                         ro.data(), kReads, haps.data(), ho.data(), kHaps, pl.data(),
                                         n_pairs, out.data(), nullptr);

@@ -132,6 +132,7 @@ struct Policy {
     uint32_t long_fp32_max_rows;
     float accept_min_sum;
     uint32_t watchdog_spins;
+    int route_diverse;      // FP32 mode: reads with unrelated haplotypes start in FP64
     float cost[2][kNumClasses];  // relative cost of one wavefront-row per class
 };
 

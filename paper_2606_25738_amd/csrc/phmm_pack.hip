@@ -6,7 +6,9 @@
 // the run's pairs greedily into 64-lane wavefronts (ceil(k/N) lanes per
 // pair, at most 32 pairs per wavefront) and emits the packs into the segment
 // of its (precision, class).  Every pack holds one read, so the per-row
-// priors and the read base are uniform across the wavefront.  Haplotypes
+// priors and the read base are uniform across the wavefront.  In FP32 mode a
+// run whose haplotypes are mutually unrelated starts in FP64 (most of its
+// pairs would be rejected by the FP32 threshold).  Haplotypes
 // longer than 64 * kMaxN columns go to the long-pair list.
 //
 // Five kernels, no contended global atomics: count (per-block segment pack
@@ -68,6 +70,65 @@ struct Greedy {
     }
 };
 
+// 4-mer presence set (256 bits) of the first kKmerBases bases of haplotype
+// h; bases are coded (c >> 1) & 3, which separates A, C, G and T ('N' shares
+// G's code, harmless for a similarity estimate).
+constexpr uint32_t kKmerBases = 32;
+__device__ void kmer_set(const Batch& b, uint32_t h, uint64_t (&m)[4])
+{
+    m[0] = m[1] = m[2] = m[3] = 0ull;
+    const uint8_t* hs = b.haps + b.hap_off[h];
+    const uint32_t n = min(hap_len(b, h), kKmerBases);
+    uint8_t c[kKmerBases];
+#pragma unroll
+    for (uint32_t j = 0; j < kKmerBases; ++j) c[j] = j < n ? hs[j] : (uint8_t)0;
+    uint32_t code = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kKmerBases; ++j) {
+        code = ((code << 2) | ((c[j] >> 1) & 3u)) & 255u;
+        if (j >= 3 && j < n) {
+            const uint64_t bit = 1ull << (code & 63u);
+            const uint32_t q = code >> 6;
+            m[0] |= q == 0 ? bit : 0ull;
+            m[1] |= q == 1 ? bit : 0ull;
+            m[2] |= q == 2 ? bit : 0ull;
+            m[3] |= q == 3 ? bit : 0ull;
+        }
+    }
+}
+
+// A run whose haplotypes are mutually unrelated: none of the next (up to)
+// three short haplotypes after the run's first shares at least half of the
+// first one's 4-mers (Jaccard index of the sets below 1/2).  Haplotypes that
+// are variants of one locus share almost all of them; unrelated 32-base
+// prefixes share about a twentieth.
+__device__ bool run_is_diverse(const Batch& b, uint64_t p, uint64_t e)
+{
+    uint64_t ref[4];
+    bool have_ref = false;
+    int compared = 0;
+    for (uint64_t q = p; q < e && compared < 3; ++q) {
+        const uint32_t h = b.pairs[2 * q + 1];
+        if (hap_len(b, h) > kShortMaxCols || hap_len(b, h) < 8) continue;
+        if (!have_ref) {
+            kmer_set(b, h, ref);
+            have_ref = true;
+            continue;
+        }
+        uint64_t m[4];
+        kmer_set(b, h, m);
+        int both = 0, any = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            both += __popcll(ref[w] & m[w]);
+            any += __popcll(ref[w] | m[w]);
+        }
+        if (2 * both >= any) return false;
+        ++compared;
+    }
+    return compared > 0;
+}
+
 // Pass 1: precision and class per run, pack counts per (segment, block);
 // long pairs to the long list.
 __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w, Policy pol)
@@ -83,7 +144,8 @@ __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w,
         const uint64_t e = run_end(b, p);
         const uint32_t r = b.pairs[2 * p];
         const uint32_t l = (uint32_t)(b.read_off[r + 1] - b.read_off[r]);
-        const int prec = (pol.precision == 1 || l > pol.fp32_max_rows) ? 1 : 0;
+        int prec = (pol.precision == 1 || l > pol.fp32_max_rows) ? 1 : 0;
+        if (prec == 0 && pol.route_diverse && e - p >= 2 && run_is_diverse(b, p, e)) prec = 1;
         const int lprec = (pol.precision == 1 || l > pol.long_fp32_max_rows) ? 1 : 0;
         Greedy g[kNumClasses];
         bool fits[kNumClasses];

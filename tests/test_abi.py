@@ -53,6 +53,7 @@ def test_default_options():
     assert o.accept_min_sum == 1e-28
     assert o.force_class == -1 and o.one_pair_per_wave == 0
     assert o.fp32_max_rows == 2048 and o.long_fp32_max_rows == 32768 and o.timing == 0
+    assert o.route_diverse_fp64 == 1
 
 
 def small_batch():

@@ -77,9 +77,12 @@ def test_cfg0_fp64_plain(ctx64):
     say("  max |dlog10| = %.3g" % d.max())
 
 
-def test_cfg0_fp32_rerun_policy(ctx32):
+def test_cfg0_fp32_rerun_policy():
+    # the one-region workload has i.i.d. haplotypes, which the packer would
+    # send to FP64 directly; here every read starts in FP32
     b = synth.generate("cfg0")
-    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    with phmm.Context(route_diverse_fp64=False) as c:
+        out, fl = phmm.phmm_forward_batch(c, b)
     want, d = check(b, out, fl)
     rerun = (fl & phmm.PHMM_FLAG_RERUN) != 0
     # pairs above the acceptance threshold are never rerun; below it a pair
@@ -89,6 +92,27 @@ def test_cfg0_fp32_rerun_policy(ctx32):
     assert np.all(rerun[want < THRESH - 200])
     say("cfg0 fp32: rerun %d of %d, max err fp32 %.3g" % (rerun.sum(), len(out),
                                                           d[~rerun].max() if (~rerun).any() else 0))
+
+
+def test_unrelated_haplotypes_start_in_fp64(ctx32):
+    """Reads whose haplotypes are mutually unrelated (the one-region workload,
+    8 i.i.d. haplotypes) run in FP64 from the start: no pair is accepted in
+    FP32 or rerun, and every result is within the FP64 bound.  Variant
+    haplotypes of one locus (the batched workload) still start in FP32."""
+    b = synth.generate("cfg0")
+    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    check(b, out, fl, plain64=True)
+    assert np.all(fl == phmm.PHMM_FLAG_FP64)
+    v = synth.generate("cfg1", 0, 30)
+    out, fl = phmm.phmm_forward_batch(ctx32, v)
+    assert ((fl & phmm.PHMM_FLAG_FP32) != 0).mean() > 0.99
+    iid = synth.generate(synth.iid_haps_cfg("cfg1"), 0, 30)
+    out, fl = phmm.phmm_forward_batch(ctx32, iid)
+    n = len(iid["pair_list"])
+    idx = np.arange(0, n, max(1, n // 300))
+    check(iid, out, fl, idx, plain64=True)
+    say("unrelated haplotypes: %d of %d pairs of the i.i.d. variant in FP64 directly"
+        % (int((fl == phmm.PHMM_FLAG_FP64).sum()), n))
 
 
 def test_cfg1_sample_fp32_rerun(ctx32):
@@ -231,7 +255,7 @@ def test_fp32_rescaled_windows_long_reads():
         b[key] = b[key][:768].copy()
     b["read_offsets"] = b["read_offsets"][:2].copy()
     b["pair_list"] = np.array([[0, 0], [0, 1]], np.uint32)
-    with phmm.Context(force_class=10) as c:
+    with phmm.Context(force_class=10, route_diverse_fp64=False) as c:
         out, fl = phmm.phmm_forward_batch(c, b)
     want, d = check(b, out, fl)
     say("mixed pack: log10 L %s, flags %s" % (np.round(want, 2), list(fl)))
