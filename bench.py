@@ -57,6 +57,18 @@ def _oracle_chunk(idx):
     return v, time.process_time() - t
 
 
+def _cpu_model():
+    """The host CPU's model name (first entry of /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def sample_pairs(batch, n_regions, seed=123):
     rp = batch["region_pairs"]
     nreg = len(rp) - 1
@@ -694,6 +706,7 @@ def main():
         log("oracle on %d pairs (%d regions, %.3g cells), %d processes" % (len(sidx), nreg, scells, cores))
         ovals, wall, cpusec = run_oracle(batch, sidx, cores)
         cpu = dict(value=round(scells / wall / 1e9, 4), unit="GCUPS", cores=cores, kind="oracle",
+                   cpu_model=_cpu_model(), single_core_gcups=round(scells / cpusec / 1e9, 4),
                    sample="%d random regions of the same workload (%d pairs, %.3g cells); "
                           "single-core %.3f GCUPS" % (nreg, len(sidx), scells,
                                                        scells / cpusec / 1e9),
