@@ -404,6 +404,34 @@ def test_cfg2_long_read_32k(ctx32):
     say("cfg2 region 32: log10 L = %.6f (oracle %.6f)" % (out[0], want[0]))
 
 
+def _golden_long(name):
+    import json
+    with open(os.path.join(ROOT, "tests", "golden", "long_reads.json")) as fh:
+        return json.load(fh)[name]
+
+
+@pytest.mark.parametrize("name", ["long_read_100k", "max_read_131072"])
+def test_longest_reads_against_stored_oracle(ctx32, name):
+    """The long-read workload's 100 kbp read (110 kbp haplotype) and a read at
+    the maximum length, 131,072 bases (144,179-base haplotype): FP64 long
+    kernel with rescaling, against oracle values stored by
+    tests/golden/make_long_reads.py (a minute or more of oracle time each)."""
+    g = _golden_long(name)
+    if name == "long_read_100k":
+        b = synth.generate("cfg2", g["region"], 1)
+    else:
+        b = synth.generate(dict(synth.CONFIGS["cfg2"], regions=1, n_len_classes=1,
+                                len_classes=(131072, 0, 0, 0), regions_per_class=1,
+                                hap_len_factor=1.1), g["region"], 1)
+    assert int(b["read_offsets"][1]) == g["read_len"] and int(b["hap_offsets"][1]) == g["hap_len"]
+    say("%s: read %d, haplotype %d" % (name, g["read_len"], g["hap_len"]))
+    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    want = float(g["log10_l"])
+    say("  log10 L = %.9f (oracle %.9f), flags 0x%02x" % (out[0], want, fl[0]))
+    assert fl[0] & phmm.PHMM_FLAG_LONG and fl[0] & phmm.PHMM_FLAG_FP64
+    assert abs(out[0] - want) <= TOL64
+
+
 def test_async_matches_sync(ctx32):
     import torch
     b = synth.generate("cfg1", 20, 10)
