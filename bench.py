@@ -43,7 +43,7 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_short_fp32_wgs.md")
 COUNTERS_PROFILE = os.path.join(ROOT, "profiles", "valu_counters_short_fp32_wgs.md")
 TRACE_PROFILE = os.path.join(ROOT, "profiles", "short_kernels_wgs_1M_regions.md")
 CSRC = os.path.join(ROOT, "paper_2606_25738_amd", "csrc")
-N_CLASSES = 11               # column classes of the short kernels (N = 4, 6, ..., 24)
+N_CLASSES = 21               # column classes of the short kernels (N = 4, 5, ..., 24)
 
 
 def log(*a):
@@ -111,7 +111,7 @@ def _pmc_rows(path, counter):
 
 def _step_dispatches(path):
     """Counter values (summed over a dispatch's rows) of the FP32 short-kernel
-    launches of the last forward pass in a rocprofv3 counter CSV: the last 22
+    launches of the last forward pass in a rocprofv3 counter CSV: the last 42
     dispatches of `short_kernel<float, c, kind>` by dispatch id.  Earlier
     dispatches (the pack-cost autotuning on a sample) are left out."""
     by = {}
@@ -155,14 +155,14 @@ def summarize_traffic(fetch_csv, write_csv, out_path, regions, calib_mib, comman
     lines = ["# HBM traffic of the FP32 short-pair kernels, genome-scale WGS-like batch", "",
              "Commands (repository root, one MI355X):", ""]
     lines += ["    " + c for c in commands]
-    lines += ["", "Workload: %d regions, one step (22 launches of `short_kernel<float, c, kind>`: the fast"
+    lines += ["", "Workload: %d regions, one step (42 launches of `short_kernel<float, c, kind>`: the fast"
               " and the general FP32 kernel of each class; counts per class summed over both). Only the"
               " launches of the last forward pass count (the pack-cost autotuning before it runs the"
               " same kernels on a sample)." % regions,
               "Counters are KiB per dispatch. Scale factor = known bytes of the calibration copy",
               "(`copy_calib_kernel`, %d MiB read and %d MiB written) / the counter's reading for it." %
               (calib_mib, calib_mib), "",
-              "| class c (N = 4 + 2c) | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---:|---:|---:|"]
+              "| class c (N = 4 + c) | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---:|---:|---:|"]
     for c in sorted(set(f["per_class"]) | set(w["per_class"])):
         lines.append("| %d | %.1f | %.1f |" % (c, f["per_class"].get(c, 0.0), w["per_class"].get(c, 0.0)))
     lines += ["", "Calibration copy: FETCH_SIZE %.1f KiB, WRITE_SIZE %.1f KiB for %d KiB each way." %
@@ -207,13 +207,13 @@ def summarize_counters(pmc_csv, bench_json, out_path, commands):
     lines = ["# VALU instruction counts of the FP32 short-pair kernels, genome-scale WGS-like batch", "",
              "Commands (repository root, one MI355X):", ""]
     lines += ["    " + c for c in commands]
-    lines += ["", "Workload: %d regions, %d pairs, %.6g cells; one forward pass (22 launches of"
+    lines += ["", "Workload: %d regions, %d pairs, %.6g cells; one forward pass (42 launches of"
               " `short_kernel<float, c, kind>`, kind 0 the fast and 1 the general FP32 kernel)."
               % (rec["config"]["regions"], rec["config"]["pairs"], cells),
               "SQ counters are wave-instructions summed over the shader engines; the clock is"
               " GRBM_GUI_ACTIVE / 8 XCDs / the dispatch's duration (under counter collection);"
               " VALU per CU-clock = SQ_INSTS_VALU / SQ_BUSY_CU_CYCLES.", "",
-              "| class c (N = 4 + 2c) | ms | VALU | FMA_F32 | MUL_F32 | ADD_F32 | INT32 | SALU |"
+              "| class c (N = 4 + c) | ms | VALU | FMA_F32 | MUL_F32 | ADD_F32 | INT32 | SALU |"
               " VALU per CU-clock | clock GHz |",
               "|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
     for d in fast:
@@ -243,7 +243,7 @@ def summarize_counters(pmc_csv, bench_json, out_path, commands):
 def summarize_trace(trace_csv, bench_json, out_path, commands):
     """Writes the kernel-duration profile of the FP32 short kernels from a
     rocprofv3 --kernel-trace run of bench.py: the forward passes on the whole
-    batch (each 22 consecutive launches of `short_kernel<float, c, kind>`; the
+    batch (each 42 consecutive launches of `short_kernel<float, c, kind>`; the
     three with the largest total, i.e. not the autotuning passes on a
     sample), beside the HIP-event figure the same run printed."""
     rec = None
@@ -282,13 +282,13 @@ def summarize_trace(trace_csv, bench_json, out_path, commands):
     lines += ["", "Workload: %d regions, %d pairs, %.6g cells. The run autotunes the pack costs on a"
               " sample before its timed steps, so the table is taken from the kernel trace"
               " (`run_kernel_trace.csv`): the %d forward calls on the whole batch (%d warm-up + %d"
-              " timed), each 22 launches of `short_kernel<float, c, kind>` (class c has N = 4 + 2c"
+              " timed), each 42 launches of `short_kernel<float, c, kind>` (class c has N = 4 + c"
               " columns per lane; kind 0 is the fast FP32 kernel, 1 the general one)."
               % (cfg["regions"], cfg["pairs"], cfg["cells"], n_big, rec["warmup"], rec["steps"]), "",
               "| kernel | calls | total us | average us |", "|---|---:|---:|---:|"]
     for name, (c, d) in sorted(per.items(), key=lambda kv: -kv[1][1]):
         lines.append("| %s | %d | %.1f | %.1f |" % (name, c, d, d / c))
-    lines += ["", "FP32 short-pair family per forward call (sum of its 22 launches): "
+    lines += ["", "FP32 short-pair family per forward call (sum of its 42 launches): "
               + ", ".join("%.1f ms" % x for x in steps_ms)
               + "; mean of the timed calls %.1f ms." % (sum(timed) / len(timed)),
               "HIP events on the launch stream in the same run (`roofline.kernel_ms`, mean of the"
@@ -777,11 +777,11 @@ def main():
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                 frac=round(achieved / FP32_PEAK_TFLOPS, 4),
                 traffic=None if traffic is None else round(traffic),
-                traffic_unit="bytes per step (22 launches)",
+                traffic_unit="bytes per step (42 launches)",
                 algorithmic_bytes=int(alg_bytes), hbm_gbs_from_traffic=None if traffic is None
                 else round(traffic / (ph["short_ms"] / 1e3) / 1e9, 2), copy_calib_gbs=copy_gbs,
-                kernel="FP32 short-pair kernels (fast and general kernel of each of the 11 column "
-                       "classes: 22 launches per step)",
+                kernel="FP32 short-pair kernels (fast and general kernel of each of the 21 column "
+                       "classes: 42 launches per step)",
                 kernel_ms=round(ph["short_ms"], 3),
                 measured_peak_fp32=round(peak32, 2), measured_peak_fp64=round(peak64, 2),
                 frac_of_measured=round(achieved / peak32, 4))

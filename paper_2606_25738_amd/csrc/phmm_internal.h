@@ -13,12 +13,11 @@ namespace phmm {
 // haplotype and calculates N elements of a M and I row").  A pair of
 // haplotype length k occupies ceil(k / N) lanes; pairs of one read are packed
 // side by side into one 64-lane wavefront.
-constexpr int kNumClasses = 11;
-__host__ __device__ constexpr int class_n(int c)
-{
-    return c == 0 ? 4 : c == 1 ? 6 : c == 2 ? 8 : c == 3 ? 10 : c == 4 ? 12 : c == 5 ? 14
-         : c == 6 ? 16 : c == 7 ? 18 : c == 8 ? 20 : c == 9 ? 22 : 24;
-}
+// N = 4, 5, ..., 24: odd widths as well as even ones, so that the packer can
+// match a read's haplotype lengths more closely (fewer idle lanes).
+constexpr int kNumClasses = 21;
+__host__ __device__ constexpr int class_n(int c) { return 4 + c; }
+__host__ __device__ constexpr int class_of_n(int n) { return n - 4; }
 constexpr int kMaxN = 24;
 constexpr int kWave = 64;
 constexpr uint32_t kShortMaxCols = kWave * kMaxN;  // longer haplotypes use the long kernel

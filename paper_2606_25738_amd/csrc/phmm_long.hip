@@ -46,14 +46,14 @@ struct LongGeom;
 template <>
 struct LongGeom<float> {
     static constexpr int N = 16;
-    static constexpr int cls = 6;                   // short-kernel class with N = 16 (scan tables)
+    static constexpr int cls = class_of_n(N);       // short-kernel class with this N (scan tables)
     static constexpr int rebase_bits = 48;          // converted records stay below 2^49
     static constexpr float exp_bias = 8388608.0f;   // 2^23: exponents stored as E + 2^23 (exact)
 };
 template <>
 struct LongGeom<double> {
     static constexpr int N = 16;
-    static constexpr int cls = 6;                   // N = 16
+    static constexpr int cls = class_of_n(N);
     static constexpr int rebase_bits = 256;
     static constexpr double exp_bias = 1099511627776.0;  // 2^40
 };

@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w,
 #pragma unroll
             for (int c = 0; c < kNumClasses; ++c)
                 if (c == best) packs = g[c].packs;
-            info = (uint32_t)best | ((uint32_t)prec << 4) | (packs << 8);
+            info = (uint32_t)best | ((uint32_t)prec << 5) | (packs << 8);
             atomicAdd(&cnt[prec * kNumClasses + best], packs);
             atomicAdd(&lanecols, (unsigned long long)packs * kWave * class_n(best));
         }
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kPackBlock) void pack_emit_kernel(Batch b, Work w, 
     if (p >= b.n_pairs || !run_start(b, p)) return;
     const uint32_t info = w.chunk_info[p];
     if (info == 0xffffffffu) return;
-    const int c = (int)(info & 15u), prec = (int)((info >> 4) & 1u);
+    const int c = (int)(info & 31u), prec = (int)((info >> 5) & 1u);
     const uint32_t npk = info >> 8;
     const int s = prec * kNumClasses + c;
     const uint32_t slot = w.ctr->pack_base[prec][c] +

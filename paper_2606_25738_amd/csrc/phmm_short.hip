@@ -81,7 +81,9 @@ constexpr int words_for(int n) { return (n + 3) / 4; }
 template <typename R, int CLS, int KIND>
 constexpr int waves_target()
 {
-    constexpr int fast_waves[kNumClasses] = {8, 7, 7, 6, 6, 6, 5, 5, 4, 4, 4};
+    // N = 4 .. 24
+    constexpr int fast_waves[kNumClasses] = {8, 7, 7, 7, 7, 6, 6, 6, 6, 6, 6,
+                                             5, 5, 5, 5, 4, 4, 4, 4, 4, 4};
     return KIND != kFast32 ? 1 : fast_waves[CLS];
 }
 

@@ -39,10 +39,10 @@ def test_exports_are_c_symbols():
 
 
 def test_classes():
-    assert phmm.phmm_num_classes() == 11
+    assert phmm.phmm_num_classes() == 21
     ns = [phmm.phmm_class_n(c) for c in range(phmm.phmm_num_classes())]
-    assert ns == [4, 6, 8, 10, 12, 14, 16, 18, 20, 22, 24]
-    assert phmm.phmm_class_n(-1) == -1 and phmm.phmm_class_n(11) == -1
+    assert ns == list(range(4, 25))
+    assert phmm.phmm_class_n(-1) == -1 and phmm.phmm_class_n(21) == -1
 
 
 def test_default_options():
@@ -136,7 +136,7 @@ def test_bad_options_rejected():
         phmm.Context(precision=7)
     assert e.value.code == phmm.PHMM_EINVAL
     with pytest.raises(phmm.PhmmError) as e:
-        phmm.Context(force_class=11)
+        phmm.Context(force_class=21)
     assert e.value.code == phmm.PHMM_EINVAL
 
 

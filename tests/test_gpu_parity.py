@@ -134,7 +134,7 @@ def test_cfg3_sample_fp32_rerun(ctx32):
     check(b, out, fl, idx)
 
 
-@pytest.mark.parametrize("cls", range(11))
+@pytest.mark.parametrize("cls", range(21))
 def test_every_class_fp32_and_fp64(cls):
     """Force each column class; pairs too long for it fall back to the widest."""
     b = synth.generate("cfg1", 100, 6)
@@ -255,7 +255,7 @@ def test_fp32_rescaled_windows_long_reads():
         b[key] = b[key][:768].copy()
     b["read_offsets"] = b["read_offsets"][:2].copy()
     b["pair_list"] = np.array([[0, 0], [0, 1]], np.uint32)
-    with phmm.Context(force_class=10, route_diverse_fp64=False) as c:
+    with phmm.Context(force_class=20, route_diverse_fp64=False) as c:
         out, fl = phmm.phmm_forward_batch(c, b)
     want, d = check(b, out, fl)
     say("mixed pack: log10 L %s, flags %s" % (np.round(want, 2), list(fl)))
@@ -507,7 +507,7 @@ def test_copy_calibration_kernel():
 def test_autotune_costs_and_results():
     with phmm.Context() as c:
         default = c.class_costs()
-        assert np.allclose(default[0], [n + 3 for n in range(4, 25, 2)])
+        assert np.allclose(default[0], [n + 3 for n in range(4, 25)])
         costs = c.autotune(seed=1)
         say("tuned ns per wave-row FP32:", np.round(costs[0], 1), "FP64:", np.round(costs[1], 1))
         assert np.all(costs > 0) and np.array_equal(costs, c.class_costs())
@@ -524,7 +524,7 @@ def test_autotune_costs_and_results():
         ws = torch.empty(phmm.phmm_workspace_bytes(c, len(b["pair_list"]), sdb.max_read_len,
                                                    sdb.max_hap_len), dtype=torch.uint8, device="cuda:0")
         picked = c.autotune_sample(sdb, ws)
-        ns = np.arange(4, 25, 2)
+        ns = np.arange(4, 25)
         fam = [np.allclose(picked[0], ns + a) for a in (0, 1, 2, 3, 5, 8, 12, 20)]
         assert any(fam) or np.array_equal(picked, costs)
         out2, fl2 = phmm.phmm_forward_batch(c, b)
