@@ -97,40 +97,50 @@ __device__ void kmer_set(const Batch& b, uint32_t h, uint64_t (&m)[4])
     }
 }
 
-// A run whose haplotypes are mutually unrelated: none of the next (up to)
-// three short haplotypes after the run's first shares at least half of the
-// first one's 4-mers (Jaccard index of the sets below 1/2).  Haplotypes that
-// are variants of one locus share almost all of them; unrelated 32-base
-// prefixes share about a twentieth.
-__device__ bool run_is_diverse(const Batch& b, uint64_t p, uint64_t e)
+// Jaccard index of two 4-mer sets at least 1/2.
+__device__ __forceinline__ bool kmer_similar(const uint64_t (&a)[4], const uint64_t (&m)[4])
 {
-    uint64_t ref[4];
-    bool have_ref = false;
-    int compared = 0;
-    for (uint64_t q = p; q < e && compared < 3; ++q) {
-        const uint32_t h = b.pairs[2 * q + 1];
-        if (hap_len(b, h) > kShortMaxCols || hap_len(b, h) < 8) continue;
-        if (!have_ref) {
-            kmer_set(b, h, ref);
-            have_ref = true;
-            continue;
-        }
-        uint64_t m[4];
-        kmer_set(b, h, m);
-        int both = 0, any = 0;
+    int both = 0, any = 0;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            both += __popcll(ref[w] & m[w]);
-            any += __popcll(ref[w] | m[w]);
-        }
-        if (2 * both >= any) return false;
-        ++compared;
+    for (int q = 0; q < 4; ++q) {
+        both += __popcll(a[q] & m[q]);
+        any += __popcll(a[q] | m[q]);
     }
-    return compared > 0;
+    return 2 * both >= any;
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, kWave);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// ceil(k / n) for k <= 2^20 and n in [4, 24]: a float estimate with the
+// reciprocal of n, then an exact fix-up (no integer division)
+__device__ __forceinline__ uint32_t ceil_div_small(uint32_t k, uint32_t n, float rcp)
+{
+    uint32_t s = (uint32_t)((float)(k + n - 1) * rcp);
+    if (s * n < k) ++s;
+    if (s > 0 && (s - 1) * n >= k) --s;
+    return s;
 }
 
 // Pass 1: precision and class per run, pack counts per (segment, block);
-// long pairs to the long list.
+// long pairs to the long list.  Each wavefront takes the runs that start in
+// its 64 pairs, nine at a time: the 7 lanes 7g .. 7g + 6 size run g, each in
+// three of the 21 classes (one greedy pass over the run; the run's
+// haplotype lengths are loaded seven at a time, one pair per lane, and
+// handed round the group), and the lowest modelled cost waves x cost[class]
+// is found across the group.  In FP32 mode a run whose haplotypes are
+// mutually unrelated (the 4-mer sets of the first 32 bases of its first short
+// haplotype and of up to three more, one set per lane: none shares half of
+// the first one's) is packed for FP64.
+constexpr int kRunLanes = 7;                           // lanes per run
+constexpr int kRunClasses = kNumClasses / kRunLanes;   // classes per lane
+constexpr int kRunsPerWave = kWave / kRunLanes;        // runs sized at once
+static_assert(kRunClasses * kRunLanes == kNumClasses, "classes split evenly over a run's lanes");
+
 __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w, Policy pol)
 {
     __shared__ uint32_t cnt[kSeg];
@@ -139,65 +149,145 @@ __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w,
     for (int q = t; q < kSeg; q += kPackBlock) cnt[q] = 0u;
     if (t == 0) lanecols = 0ull;
     __syncthreads();
-    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + t;
-    if (p < b.n_pairs && run_start(b, p)) {
-        const uint64_t e = run_end(b, p);
-        const uint32_t r = b.pairs[2 * p];
-        const uint32_t l = (uint32_t)(b.read_off[r + 1] - b.read_off[r]);
-        int prec = (pol.precision == 1 || l > pol.fp32_max_rows) ? 1 : 0;
-        if (prec == 0 && pol.route_diverse && e - p >= 2 && run_is_diverse(b, p, e)) prec = 1;
-        const int lprec = (pol.precision == 1 || l > pol.long_fp32_max_rows) ? 1 : 0;
-        Greedy g[kNumClasses];
-        bool fits[kNumClasses];
+    const int lane = t & (kWave - 1);
+    const uint64_t p0 = (uint64_t)blockIdx.x * blockDim.x + (uint64_t)(t - lane);
+    const uint64_t mine = p0 + (uint64_t)lane;
+    uint64_t starts = __ballot(mine < b.n_pairs && run_start(b, mine));
+    const int g = lane / kRunLanes, sub = lane - g * kRunLanes;  // g = 9: idle lane
+    const int lead = g * kRunLanes;
+    float rcp[kRunClasses];
 #pragma unroll
-        for (int c = 0; c < kNumClasses; ++c) {
-            g[c].reset();
-            fits[c] = true;
+    for (int i = 0; i < kRunClasses; ++i) rcp[i] = 1.0f / (float)class_n(sub * kRunClasses + i);
+    while (starts) {  // wave-uniform
+        // the g-th of the next kRunsPerWave run starts
+        uint64_t rest = starts;
+        for (int j = 0; j < g && rest; ++j) rest &= rest - 1;
+        const bool active = g < kRunsPerWave && rest != 0ull;
+        const uint64_t p = active ? p0 + (uint64_t)(__ffsll((unsigned long long)rest) - 1) : 0ull;
+        for (int j = 0; j < kRunsPerWave && starts; ++j) starts &= starts - 1;
+        const uint64_t e = active ? run_end(b, p) : p;
+        uint32_t l = 0;
+        if (active) {
+            const uint32_t r = b.pairs[2 * p];
+            l = (uint32_t)(b.read_off[r + 1] - b.read_off[r]);
+        }
+        int prec = (pol.precision == 1 || l > pol.fp32_max_rows) ? 1 : 0;
+        const int lprec = (pol.precision == 1 || l > pol.long_fp32_max_rows) ? 1 : 0;
+        // this lane's classes sub * kRunClasses + i over the run
+        Greedy gr[kRunClasses];
+        bool fits[kRunClasses];
+#pragma unroll
+        for (int i = 0; i < kRunClasses; ++i) {
+            gr[i].reset();
+            fits[i] = true;
         }
         uint32_t nshort = 0;
-        for (uint64_t q = p; q < e; ++q) {
-            const uint32_t k = hap_len(b, b.pairs[2 * q + 1]);
-            if (k > kShortMaxCols) {
+        for (uint64_t base = p; base < e; base += kRunLanes) {
+            const uint64_t mine_q = base + (uint64_t)sub;
+            const uint32_t mine_k = mine_q < e ? hap_len(b, b.pairs[2 * mine_q + 1]) : 0u;
+            if (mine_k > kShortMaxCols) {  // this lane's pair is long
                 const uint32_t idx = atomicAdd(&w.ctr->n_long[lprec], 1u);
-                w.long_list[lprec][idx] = (uint32_t)q;
+                w.long_list[lprec][idx] = (uint32_t)mine_q;
+            }
+            const int m = (int)min<uint64_t>((uint64_t)kRunLanes, e - base);
+            for (int j = 0; j < m; ++j) {
+                const uint32_t k = (uint32_t)__shfl((int)mine_k, lead + j, kWave);
+                if (k > kShortMaxCols) {
 #pragma unroll
-                for (int c = 0; c < kNumClasses; ++c) {
-                    g[c].used = kWave;
-                    g[c].np = 0;
+                    for (int i = 0; i < kRunClasses; ++i) {
+                        gr[i].used = kWave;
+                        gr[i].np = 0;
+                    }
+                    continue;
                 }
+                ++nshort;
+#pragma unroll
+                for (int i = 0; i < kRunClasses; ++i) {
+                    const uint32_t N = (uint32_t)class_n(sub * kRunClasses + i);
+                    const uint32_t sl = ceil_div_small(k, N, rcp[i]);
+                    if (sl > (uint32_t)kWave) fits[i] = false;
+                    else gr[i].add(sl, pol.one_pair_per_wave);
+                }
+            }
+        }
+        // unrelated haplotypes: lanes sub = 0..3 take the run's sub-th short
+        // haplotype of at least 8 bases
+        const bool check = active && prec == 0 && pol.route_diverse && e - p >= 2;
+        uint64_t km[4] = {0ull, 0ull, 0ull, 0ull};
+        bool have = false;
+        if (check && sub < 4) {
+            int seen = 0;
+            for (uint64_t q = p; q < e; ++q) {
+                const uint32_t h = b.pairs[2 * q + 1];
+                const uint32_t k = hap_len(b, h);
+                if (k > kShortMaxCols || k < 8) continue;
+                if (seen == sub) {
+                    kmer_set(b, h, km);
+                    have = true;
+                    break;
+                }
+                ++seen;
+            }
+        }
+        const int src = active ? lead : lane;
+        uint64_t ref[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ref[q] = shfl64(km[q], src);
+        const bool ref_ok = __shfl((int)have, src, kWave) != 0;
+        const int cmp = (have && sub > 0 && sub < 4 && ref_ok) ? 1 : 0;
+        const int similar = cmp && kmer_similar(ref, km) ? 1 : 0;
+        int any_similar = 0, n_compared = 0;
+        for (int j = 1; j < 4; ++j) {
+            any_similar |= __shfl(similar, src + j, kWave);
+            n_compared += __shfl(cmp, src + j, kWave);
+        }
+        if (check && n_compared > 0 && !any_similar) prec = 1;
+        // the class with the lowest modelled cost: first over this lane's
+        // classes, then over the group's lanes (first minimum in class order)
+        float my_cost = 3.0e38f;
+        int my_cls = -1;
+        uint32_t my_packs = 0;
+#pragma unroll
+        for (int i = 0; i < kRunClasses; ++i) {
+            const int cls = sub * kRunClasses + i;
+            if (!active || nshort == 0 || !fits[i] || (pol.force_class >= 0 && cls != pol.force_class))
                 continue;
-            }
-            ++nshort;
-#pragma unroll
-            for (int c = 0; c < kNumClasses; ++c) {
-                const uint32_t s = (k + class_n(c) - 1) / class_n(c);
-                if (s > (uint32_t)kWave) fits[c] = false;
-                else g[c].add(s, pol.one_pair_per_wave);
+            const float v = (float)gr[i].packs * pol.cost[prec][cls];
+            if (v < my_cost) {
+                my_cost = v;
+                my_cls = cls;
+                my_packs = gr[i].packs;
             }
         }
-        uint32_t info = 0xffffffffu;
-        if (nshort > 0) {
-            int best = -1;
-            float best_cost = 0.f;
-#pragma unroll
-            for (int c = 0; c < kNumClasses; ++c) {
-                if ((pol.force_class >= 0 && c != pol.force_class) || !fits[c]) continue;
-                const float cost = (float)g[c].packs * pol.cost[prec][c];
-                if (best < 0 || cost < best_cost) {
-                    best = c;
-                    best_cost = cost;
+        float best_cost = 3.0e38f;
+        int best = -1;
+        uint32_t best_packs = 0;
+        for (int j = 0; j < kRunLanes; ++j) {
+            const float v = __shfl(my_cost, src + j, kWave);
+            const int cl = __shfl(my_cls, src + j, kWave);
+            const uint32_t pk = (uint32_t)__shfl((int)my_packs, src + j, kWave);
+            if (v < best_cost) {
+                best_cost = v;
+                best = cl;
+                best_packs = pk;
+            }
+        }
+        // forced class too narrow: the widest (held by the group's last lane)
+        const uint32_t widest_packs =
+            (uint32_t)__shfl((int)gr[kRunClasses - 1].packs, src + kRunLanes - 1, kWave);
+        if (active && sub == 0) {
+            uint32_t info = 0xffffffffu;
+            if (nshort > 0) {
+                if (best < 0) {
+                    best = kNumClasses - 1;
+                    best_packs = widest_packs;
                 }
+                info = (uint32_t)best | ((uint32_t)prec << 5) | (best_packs << 8);
+                atomicAdd(&cnt[prec * kNumClasses + best], best_packs);
+                atomicAdd(&lanecols, (unsigned long long)best_packs * kWave * class_n(best));
             }
-            if (best < 0) best = kNumClasses - 1;  // forced class too narrow: the widest
-            uint32_t packs = 0;
-#pragma unroll
-            for (int c = 0; c < kNumClasses; ++c)
-                if (c == best) packs = g[c].packs;
-            info = (uint32_t)best | ((uint32_t)prec << 5) | (packs << 8);
-            atomicAdd(&cnt[prec * kNumClasses + best], packs);
-            atomicAdd(&lanecols, (unsigned long long)packs * kWave * class_n(best));
+            w.chunk_info[p] = info;
         }
-        w.chunk_info[p] = info;
     }
     __syncthreads();
     for (int q = t; q < kSeg; q += kPackBlock)
