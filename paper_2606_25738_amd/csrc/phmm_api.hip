@@ -318,15 +318,25 @@ static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s)
     if (b.n_pairs > 0) launch_pack(s, b, w, pol);
     if (timed) HIP_TRY(hipEventRecord(c->ev[1], s));
     if (b.n_pairs > 0) {
+        // Without reading the device counters the launch set is fixed: every
+        // class of every family, even when it has nothing to do.  A launch's
+        // cost with no work grows with its workgroup count, so no grid is
+        // larger than the batch's pair count (a bound on any class's packs
+        // or items), and the general FP32 kernels, which only run packs the
+        // fast kernels defer (reads with per-row gap penalties, a gap byte of
+        // 0 or an insertion byte above 65), get one wavefront per SIMD.
+        const int n_cap = (int)std::min<uint64_t>(b.n_pairs, 1u << 30);
+        auto cap = [&](int grid) { return std::min(grid, n_cap); };
         if (pol.precision == PHMM_FP32_RERUN) {
             for (int cls = 0; cls < kNumClasses; ++cls)
-                launch_short(kFast32, cls, c->grid_short[kFast32][cls], s, b, t, w, pol);
+                launch_short(kFast32, cls, cap(c->grid_short[kFast32][cls]), s, b, t, w, pol);
             for (int cls = 0; cls < kNumClasses; ++cls)
-                launch_short(kGen32, cls, c->grid_short[kGen32][cls], s, b, t, w, pol);
+                launch_short(kGen32, cls, cap(std::min(c->grid_short[kGen32][cls], 4 * c->cus)), s,
+                             b, t, w, pol);
         }
         if (timed) HIP_TRY(hipEventRecord(c->ev[2], s));
         for (int cls = 0; cls < kNumClasses; ++cls)
-            launch_short(kAll64, cls, c->grid_short[kAll64][cls], s, b, t, w, pol);
+            launch_short(kAll64, cls, cap(c->grid_short[kAll64][cls]), s, b, t, w, pol);
         if (timed) HIP_TRY(hipEventRecord(c->ev[3], s));
         launch_long(s, c->grid_long, b, t, w, pol);
     } else if (timed) {
