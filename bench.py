@@ -229,7 +229,11 @@ def summarize_counters(pmc_csv, bench_json, out_path, commands):
               "- valu_lane_instructions_per_cell: %.3f" % lane,
               "- fp32_fma_mul_add_lane_instructions_per_cell: %.3f" % fp,
               "- int32_lane_instructions_per_cell: %.3f" % (64.0 * tot["SQ_INSTS_VALU_INT32"] / cells),
-              "- counted_fp32_flops_per_cell: %.3f" % (tot["SQ_INSTS_VALU_FLOPS_FP32"] / cells),
+              "- fp32_flops_counter_per_cell: %.4f (the counter counts per wave-instruction; x 64 lanes: %.2f,"
+              " against 2 x FMA + MUL + ADD from the instruction counters x 64: %.2f)"
+              % (tot["SQ_INSTS_VALU_FLOPS_FP32"] / cells, 64.0 * tot["SQ_INSTS_VALU_FLOPS_FP32"] / cells,
+                 64.0 * (2.0 * tot["SQ_INSTS_VALU_FMA_F32"] + tot["SQ_INSTS_VALU_MUL_F32"]
+                         + tot["SQ_INSTS_VALU_ADD_F32"]) / cells),
               "- algorithmic_flops_per_cell: %d" % FLOPS_PER_CELL,
               "- valu_per_cu_clock: %.3f" % (tot["SQ_INSTS_VALU"] / max(1.0, tot["SQ_BUSY_CU_CYCLES"])),
               "- clock_ghz: %.3f" % (tot["GRBM_GUI_ACTIVE"] / 8.0 / max(1, ns)),
