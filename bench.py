@@ -733,10 +733,10 @@ def main():
     ctx = phmm.Context(timing=True)
     costs = None
     if not args.no_autotune:
-        # per-class costs measured on a synthetic batch, then the table that
-        # runs a sample of this workload (its first 50,000 regions) fastest
+        # the cost table (N + a, a from a fixed set, or the default N + 3)
+        # that runs a sample of this workload (its first 50,000 regions)
+        # fastest
         t = time.perf_counter()
-        ctx.autotune(seed=0)
         ns = min(args.regions, 50000)
         sb = synth.generate("cfg3", 0, ns)
         sdb = phmm.DeviceBatch(sb, "cuda:0")
