@@ -118,6 +118,35 @@ def test_validate_ranges():
     expect(phmm.PHMM_ERANGE, b, "read 0")
 
 
+def test_validate_large_batch_reports_first_error():
+    """Arrays large enough to be checked in parallel blocks (2^26 read bases,
+    2^25 pairs, 2^25 reads): each error is reported at the first offending
+    index, as a sequential scan would, whichever block finds it first."""
+    nr = 1 << 25  # reads of 2 bases
+    nb = 2 * nr
+    b = dict(reads=np.full(nb, ord("A"), np.uint8), base_quals=np.full(nb, 30, np.uint8),
+             ins_quals=np.full(nb, 45, np.uint8), del_quals=np.full(nb, 45, np.uint8),
+             gcp=np.full(nb, 10, np.uint8),
+             read_offsets=np.arange(0, nb + 1, 2, dtype=np.uint64),
+             haplotypes=np.full(8, ord("C"), np.uint8), hap_offsets=np.array([0, 8], np.uint64),
+             pair_list=np.zeros((nr, 2), np.uint32))
+    b["pair_list"][:, 0] = np.arange(nr, dtype=np.uint32)
+    assert phmm.phmm_validate_batch(b) == (2, 8)
+    b["reads"][nb - 3] = ord("x")
+    b["reads"][nb // 2 + 5] = ord("Z")
+    b["reads"][12345678] = ord("U")
+    expect(phmm.PHMM_EINVAL, b, "read base 12345678 ")
+    b["reads"][[12345678, nb // 2 + 5, nb - 3]] = ord("G")
+    b["pair_list"][nr - 1, 1] = 1
+    b["pair_list"][20000000, 1] = 5
+    expect(phmm.PHMM_EINVAL, b, "pair 20000000:")
+    b["pair_list"][[nr - 1, 20000000], 1] = 0
+    ro = b["read_offsets"]
+    ro[30000001] = ro[30000000]  # read 30000000 is empty
+    ro[nr - 1] = ro[nr - 2]
+    expect(phmm.PHMM_EINVAL, b, "read 30000000 ")
+
+
 def test_validate_empty_batch_is_fine():
     b = small_batch()
     b["pair_list"] = np.zeros((0, 2), np.uint32)
