@@ -651,7 +651,8 @@ def main():
     ap.add_argument("--sweep-reps", type=int, default=3)
     ap.add_argument("--small-batch", action="store_true",
                     help="run only the small-batch latency leg (about 3550 short pairs)")
-    ap.add_argument("--small-reps", type=int, default=50)
+    ap.add_argument("--small-reps", type=int, default=50,
+                    help="calls timed in the small-batch leg (0 = skip it in the default run)")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic profile from two rocprofv3 --pmc runs (no GPU used)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("PMC_CSV", "BENCH_JSON"),
@@ -824,6 +825,7 @@ def main():
     torch.cuda.empty_cache()
     opw = one_pair_per_wave_leg(phmm, torch, args, costs) if args.opw_regions > 0 else None
     uneven = batched_uneven_leg(phmm, torch, args) if args.uneven else None
+    small = small_batch_leg(phmm, torch, args) if args.small_reps > 0 else None
     serving = serve_leg(phmm, args) if args.serve_seconds > 0 else None
 
     parity = None
@@ -856,7 +858,7 @@ def main():
         pack_costs=None if costs is None else dict(fp32=np.round(costs[0], 3).tolist(),
                                                    fp64=np.round(costs[1], 3).tolist()),
         fp64_plain=fp64, fp64_one_pair_per_wave=opw, end_to_end=end_to_end,
-        batched_uneven=uneven, parity_sample=parity, serving=serving,
+        batched_uneven=uneven, small_batch=small, parity_sample=parity, serving=serving,
     )
     print(json.dumps(rec), flush=True)
 
