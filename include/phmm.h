@@ -153,7 +153,11 @@ int phmm_class_n(int c);
  * n_pairs == 0 is valid and does nothing.
  *
  * The host reads the device's counters between kernel families and
- * launches only kernels that have work.  A batch of 2^23 pairs or more is
+ * launches only kernels that have work.  A batch of at most 8192 pairs
+ * (unless options.force_class is set) packs every pair in the narrowest
+ * column class whose 64 lanes hold its longest short haplotype (one launch
+ * per kernel family; the results agree with the cost model's packing to
+ * rounding).  A batch of 2^23 pairs or more is
  * split into up to 16 chunks of consecutive pairs; the inputs a chunk needs
  * are copied on a second stream while the chunks before it compute
  * (phmm_last_timing then describes the last chunk's pass).  Inputs need not

@@ -356,9 +356,24 @@ static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s)
 // with nothing to do still dispatches every workgroup of its grid (tens of
 // microseconds each), which dominates a small batch; the read-backs cost
 // about as much as one such launch each.
-static int enqueue_sync(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s)
+//
+// A small batch (at most kSmallBatchPairs pairs) cannot fill the GPU, so its
+// time is launches and the longest wavefront, not throughput: unless a class
+// is forced, every pack gets the narrowest class whose 64 lanes hold the
+// batch's longest short haplotype (max_hap_len, capped at the short limit).
+// One class means one launch per kernel family, and a narrow class a short
+// row loop.
+constexpr uint64_t kSmallBatchPairs = 8192;
+
+static int enqueue_sync(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s,
+                        uint32_t max_hap_len)
 {
-    const Policy pol = make_policy(c->opt, c->cost);
+    Policy pol = make_policy(c->opt, c->cost);
+    if (b.n_pairs <= kSmallBatchPairs && pol.force_class < 0) {
+        const uint32_t k = std::max(1u, std::min(max_hap_len, kShortMaxCols));
+        const int n = std::max(class_n(0), (int)((k + kWave - 1) / kWave));
+        pol.force_class = class_of_n(std::min(n, kMaxN));
+    }
     Tables t;
     t.p64 = c->d_p64;
     t.pw64 = c->d_pw64;
@@ -465,7 +480,7 @@ int phmm::forward_device_batch_sync(phmm_ctx* c, const phmm_device_batch* db, do
     const int rc = device_batch(c, db, d_out, d_flags, d_ws, ws_bytes, &b);
     if (rc != PHMM_OK) return rc;
     HIP_TRY(hipSetDevice(c->device));
-    return enqueue_sync(c, b, d_ws, s);
+    return enqueue_sync(c, b, d_ws, s, db->max_hap_len);
 }
 
 extern "C" int phmm_device_status(phmm_ctx* c, void* d_ws)
@@ -769,7 +784,7 @@ extern "C" int phmm_forward_batch(phmm_ctx* c, const uint8_t* reads, const uint8
             return rc;
         HIP_TRY(hipMemcpyAsync(A + o_ro, ro, ((size_t)n_reads + 1) * 8, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(A + o_ho, ho, ((size_t)n_haps + 1) * 8, hipMemcpyHostToDevice, s));
-        rc = enqueue_sync(c, b, A + o_ws, s);
+        rc = enqueue_sync(c, b, A + o_ws, s, max_k);
         if (rc != PHMM_OK) return rc;
         HIP_TRY(hipMemcpyAsync(c->h_ctr, A + o_ws, sizeof(Counters), hipMemcpyDeviceToHost, s));
     } else {
