@@ -304,9 +304,36 @@ static Work work_for(phmm_ctx* c, void* ws, uint64_t n_pairs)
 }
 
 // ---------------------------------------------------------------- launch
-static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s)
+// A small batch (at most kSmallBatchPairs pairs) cannot fill the GPU, so its
+// time is launches and the longest wavefront, not throughput: unless a class
+// is forced, every pack gets the narrowest class whose 64 lanes hold the
+// batch's longest short haplotype (max_hap_len, capped at the short limit).
+// One class means one launch per kernel family, and a narrow class a short
+// row loop.
+constexpr uint64_t kSmallBatchPairs = 8192;
+
+static Policy batch_policy(phmm_ctx* c, uint64_t n_pairs, uint32_t max_hap_len)
 {
-    const Policy pol = make_policy(c->opt, c->cost);
+    Policy pol = make_policy(c->opt, c->cost);
+    if (n_pairs <= kSmallBatchPairs && pol.force_class < 0) {
+        const uint32_t k = std::max(1u, std::min(max_hap_len, kShortMaxCols));
+        const int n = std::max(class_n(0), (int)((k + kWave - 1) / kWave));
+        pol.force_class = class_of_n(std::min(n, kMaxN));
+    }
+    return pol;
+}
+
+// Whether class cls can receive packs under pol: with a class forced, only
+// that one and the widest (a run whose haplotypes do not fit the forced class
+// falls back to the widest).
+static bool class_used(const Policy& pol, int cls)
+{
+    return pol.force_class < 0 || cls == pol.force_class || cls == kNumClasses - 1;
+}
+
+static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s, uint32_t max_hap_len)
+{
+    const Policy pol = batch_policy(c, b.n_pairs, max_hap_len);
     Tables t;
     t.p64 = c->d_p64;
     t.pw64 = c->d_pw64;
@@ -329,14 +356,17 @@ static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s)
         auto cap = [&](int grid) { return std::min(grid, n_cap); };
         if (pol.precision == PHMM_FP32_RERUN) {
             for (int cls = 0; cls < kNumClasses; ++cls)
-                launch_short(kFast32, cls, cap(c->grid_short[kFast32][cls]), s, b, t, w, pol);
+                if (class_used(pol, cls))
+                    launch_short(kFast32, cls, cap(c->grid_short[kFast32][cls]), s, b, t, w, pol);
             for (int cls = 0; cls < kNumClasses; ++cls)
-                launch_short(kGen32, cls, cap(std::min(c->grid_short[kGen32][cls], 4 * c->cus)), s,
-                             b, t, w, pol);
+                if (class_used(pol, cls))
+                    launch_short(kGen32, cls, cap(std::min(c->grid_short[kGen32][cls], 4 * c->cus)),
+                                 s, b, t, w, pol);
         }
         if (timed) HIP_TRY(hipEventRecord(c->ev[2], s));
         for (int cls = 0; cls < kNumClasses; ++cls)
-            launch_short(kAll64, cls, cap(c->grid_short[kAll64][cls]), s, b, t, w, pol);
+            if (class_used(pol, cls))
+                launch_short(kAll64, cls, cap(c->grid_short[kAll64][cls]), s, b, t, w, pol);
         if (timed) HIP_TRY(hipEventRecord(c->ev[3], s));
         launch_long(s, c->grid_long, b, t, w, pol);
     } else if (timed) {
@@ -356,24 +386,10 @@ static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s)
 // with nothing to do still dispatches every workgroup of its grid (tens of
 // microseconds each), which dominates a small batch; the read-backs cost
 // about as much as one such launch each.
-//
-// A small batch (at most kSmallBatchPairs pairs) cannot fill the GPU, so its
-// time is launches and the longest wavefront, not throughput: unless a class
-// is forced, every pack gets the narrowest class whose 64 lanes hold the
-// batch's longest short haplotype (max_hap_len, capped at the short limit).
-// One class means one launch per kernel family, and a narrow class a short
-// row loop.
-constexpr uint64_t kSmallBatchPairs = 8192;
-
 static int enqueue_sync(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s,
                         uint32_t max_hap_len)
 {
-    Policy pol = make_policy(c->opt, c->cost);
-    if (b.n_pairs <= kSmallBatchPairs && pol.force_class < 0) {
-        const uint32_t k = std::max(1u, std::min(max_hap_len, kShortMaxCols));
-        const int n = std::max(class_n(0), (int)((k + kWave - 1) / kWave));
-        pol.force_class = class_of_n(std::min(n, kMaxN));
-    }
+    const Policy pol = batch_policy(c, b.n_pairs, max_hap_len);
     Tables t;
     t.p64 = c->d_p64;
     t.pw64 = c->d_pw64;
@@ -470,7 +486,7 @@ extern "C" int phmm_forward_batch_async(phmm_ctx* c, const phmm_device_batch* db
     const int rc = device_batch(c, db, d_out, d_flags, d_ws, ws_bytes, &b);
     if (rc != PHMM_OK) return rc;
     HIP_TRY(hipSetDevice(c->device));
-    return enqueue(c, b, d_ws, static_cast<hipStream_t>(hip_stream));
+    return enqueue(c, b, d_ws, static_cast<hipStream_t>(hip_stream), db->max_hap_len);
 }
 
 int phmm::forward_device_batch_sync(phmm_ctx* c, const phmm_device_batch* db, double* d_out,
@@ -817,7 +833,7 @@ extern "C" int phmm_forward_batch(phmm_ctx* c, const uint8_t* reads, const uint8
             bk.n_pairs = p0[k + 1] - p0[k];
             bk.out = b.out + p0[k];
             bk.flags = b.flags + p0[k];
-            rc = enqueue(c, bk, A + o_ws, s);
+            rc = enqueue(c, bk, A + o_ws, s, max_k);
             if (rc != PHMM_OK) return rc;
             HIP_TRY(hipMemcpyAsync(c->h_chunk + k, A + o_ws, sizeof(Counters), hipMemcpyDeviceToHost, s));
         }
