@@ -226,10 +226,10 @@ size_t phmm_workspace_bytes(phmm_ctx* ctx, uint64_t n_pairs, uint32_t max_read_l
  * NULL) are device pointers; d_workspace holds at least
  * phmm_workspace_bytes(...) bytes of device memory.  Only the host-visible
  * fields of *b are checked (null pointers, bounds, workspace size); device
- * contents are trusted; a batch of at most 8192 pairs is packed in one
+ * contents are trusted.  A batch of at most 8192 pairs is packed in one
  * narrow class chosen from max_hap_len, as in phmm_forward_batch.  Errors
- * detected on the device (watchdog) are
- * reported by phmm_device_status() after the stream has passed the call.
+ * detected on the device (watchdog) are reported by phmm_device_status()
+ * after the stream has passed the call.
  */
 int phmm_forward_batch_async(phmm_ctx* ctx, const phmm_device_batch* b, double* d_out_log10,
                              uint8_t* d_flags, void* d_workspace, size_t ws_bytes,

@@ -471,6 +471,31 @@ def test_async_matches_sync(ctx32):
     check(b, sync_out, sync_fl, np.arange(0, n, max(1, n // 300)))
 
 
+def test_small_async_batches_one_class_and_fallbacks():
+    """Small batches through the stream-ordered call: packed in one narrow
+    class (with short and long pairs mixed), and with a forced class too
+    narrow for some haplotypes, whose runs fall back to the widest class;
+    every result against the oracle."""
+    rng = np.random.default_rng(17)
+    pairs = []
+    for l, k in ((120, 150), (120, 300), (140, 600), (100, 1536), (200, 1600), (150, 2300)):
+        hap = rnd(rng, k)
+        off = int(rng.integers(0, k - l)) if k > l else 0
+        read = bytearray(hap[off:off + l])
+        for j in rng.integers(0, l, l // 40):
+            read[j] = ord("ACGT"[int(rng.integers(0, 4))])
+        pairs.append((bytes(read), hap, rng.integers(10, 41, l), 45, 45, 10))
+    b = make_batch(pairs)
+    with phmm.Context() as c:
+        out, fl, _ = _async_pass(c, b)
+    check(b, out, fl)
+    assert ((fl & phmm.PHMM_FLAG_LONG) != 0).sum() == 2
+    sub = make_batch(pairs[:3])  # haplotypes of 150-600 bases
+    with phmm.Context(force_class=0) as c:  # N = 4 holds at most 256 columns
+        out, fl, _ = _async_pass(c, sub)
+    check(sub, out, fl)
+
+
 def test_chunked_sync_call_matches_async(ctx32):
     """A synchronous call large enough to be split into chunks of pairs (its
     inputs copied chunk by chunk while earlier chunks compute) gives the
