@@ -337,7 +337,7 @@ def serve_leg(phmm, args):
     def region(i):
         c = i // gen_chunk
         if c not in cache:
-            cache[c] = synth.generate("cfg4", c * gen_chunk, gen_chunk)
+            cache[c] = synth.generate("served_stream", c * gen_chunk, gen_chunk)
         return synth.region_slice(cache[c], i - c * gen_chunk)
 
     opts = dict(lanes=args.serve_lanes, long_lanes=1, hbm_budget_bytes=args.serve_budget_gib << 30,
@@ -520,7 +520,7 @@ def batched_uneven_leg(phmm, torch, args):
     i.i.d. haplotypes, in FP32 + rerun and in plain FP64: kernel-only GCUPS
     and the share of pairs rerun in FP64."""
     res = {}
-    for name, cfg in (("variant_haplotypes", "cfg1"), ("iid_haplotypes", synth.iid_haps_cfg("cfg1"))):
+    for name, cfg in (("variant_haplotypes", "batched_uneven"), ("iid_haplotypes", synth.iid_haps_cfg("batched_uneven"))):
         b = synth.generate(cfg)
         cells = int(pair_cells(b)[0].sum())
         db = phmm.DeviceBatch(b, "cuda:0")
@@ -545,7 +545,7 @@ def one_pair_per_wave_leg(phmm, torch, args, costs):
     """FP64 on the first `args.opw_regions` regions of the genome-scale
     workload in two forms: one pair per wavefront (no packing) and packed as
     the FP64 path runs it, beside FP32 + rerun on the same pairs."""
-    b = synth.generate("cfg3", 0, args.opw_regions)
+    b = synth.generate("genome_scale", 0, args.opw_regions)
     cells = int(pair_cells(b)[0].sum())
     db = phmm.DeviceBatch(b, "cuda:0")
     res = {"regions": args.opw_regions, "pairs": db.n_pairs, "cells": cells}
@@ -695,7 +695,7 @@ def main():
         return
 
     t = time.perf_counter()
-    batch = synth.generate("cfg3", 0, args.regions)
+    batch = synth.generate("genome_scale", 0, args.regions)
     cells_pp, rl, hl = pair_cells(batch)
     cells = int(cells_pp.sum())
     n_pairs = len(cells_pp)
@@ -739,7 +739,7 @@ def main():
         # fastest
         t = time.perf_counter()
         ns = min(args.regions, 50000)
-        sb = synth.generate("cfg3", 0, ns)
+        sb = synth.generate("genome_scale", 0, ns)
         sdb = phmm.DeviceBatch(sb, "cuda:0")
         sws = torch.empty(phmm.phmm_workspace_bytes(ctx, len(sb["pair_list"]), sdb.max_read_len,
                                                     sdb.max_hap_len), dtype=torch.uint8, device="cuda:0")

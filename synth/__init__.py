@@ -20,14 +20,15 @@ boundary:
 Workloads (the paper's real data sets are not available; these stand in for
 them with the published shapes only):
 
-  cfg0  one region, 8 i.i.d. haplotypes x 200 bp, 64 reads x 100 bp
-  cfg1  20,000 regions, 2-8 variant haplotypes of 150-600 bp, lognormal reads
-        (mean 40, sigma 1, cap 400) of 100-150 bp
-  cfg2  96 long pairs: 32 each of 10k, 32k and 100k bp, haplotype 1.1x read
-  cfg3  genome-scale: regions of 150 bp reads, 2-16 variant haplotypes of
-        150-600 bp, lognormal read counts, qualities Phred 2-41
-  cfg4  served stream: cfg3 regions, 5% of them long-read regions (reads of
-        1k-20k bp, 2-4 haplotypes of 1.1x read length)
+  one_region      one region, 8 i.i.d. haplotypes x 200 bp, 64 reads x 100 bp
+  batched_uneven  20,000 regions, 2-8 variant haplotypes of 150-600 bp,
+                  lognormal reads (mean 40, sigma 1, cap 400) of 100-150 bp
+  long_reads      96 long pairs: 32 each of 10k, 32k and 100k bp, haplotype
+                  1.1x read
+  genome_scale    regions of 150 bp reads, 2-16 variant haplotypes of
+                  150-600 bp, lognormal read counts, qualities Phred 2-41
+  served_stream   genome_scale regions, 5% of them long-read regions (reads
+                  of 1k-20k bp, 2-4 haplotypes of 1.1x read length)
 """
 from __future__ import annotations
 
@@ -91,17 +92,17 @@ _BASE = dict(n_haps_lo=8, n_haps_hi=8, hap_len_lo=200, hap_len_hi=200, hap_mode=
 
 CONFIGS = {
     # one region, plain FP64 (8 i.i.d. haps x 200 bp, 64 reads x 100 bp)
-    "cfg0": dict(_BASE, regions=1, seed=0),
+    "one_region": dict(_BASE, regions=1, seed=0),
     # batched uneven short pairs
-    "cfg1": dict(_BASE, regions=20000, seed=1, n_haps_lo=2, n_haps_hi=8, hap_len_lo=150,
+    "batched_uneven": dict(_BASE, regions=20000, seed=1, n_haps_lo=2, n_haps_hi=8, hap_len_lo=150,
                  hap_len_hi=600, hap_mode=1, reads_mode=1, read_len_lo=100, read_len_hi=150),
     # long-read pairs (one read x one hap per region), 32 each of three lengths
-    "cfg2": dict(_BASE, regions=96, seed=2, n_haps_lo=1, n_haps_hi=1, reads_fixed=1,
+    "long_reads": dict(_BASE, regions=96, seed=2, n_haps_lo=1, n_haps_hi=1, reads_fixed=1,
                  n_len_classes=3, len_classes=(10000, 32000, 100000, 0), regions_per_class=32,
                  hap_len_factor=1.1, p_sub=0.05, p_indel=0.02, indel_lo=1, indel_hi=10,
                  q_lo=5, q_hi=30, ins_q=30, del_q=30, offset_mode=1, offset_frac=0.05),
     # genome-scale WGS-like regions (generated in chunks of regions)
-    "cfg3": dict(_BASE, regions=1000000, seed=3, n_haps_lo=2, n_haps_hi=16, hap_len_lo=150,
+    "genome_scale": dict(_BASE, regions=1000000, seed=3, n_haps_lo=2, n_haps_hi=16, hap_len_lo=150,
                  hap_len_hi=600, hap_mode=1, reads_mode=1, read_len_lo=150, read_len_hi=150,
                  p_sub=0.005, p_indel=0.0005, q_lo=2, q_hi=41),
 }
@@ -109,7 +110,7 @@ CONFIGS = {
 # long (all reads of one length U{1000..20000}, 2-4 haplotypes of 1.1x that
 # length, same error and quality model); the region count is a pool the
 # arrival process draws from in order
-CONFIGS["cfg4"] = dict(CONFIGS["cfg3"], regions=1000000, seed=4, long_frac=0.05,
+CONFIGS["served_stream"] = dict(CONFIGS["genome_scale"], regions=1000000, seed=4, long_frac=0.05,
                        long_len_lo=1000, long_len_hi=20000, long_haps_lo=2, long_haps_hi=4,
                        long_hap_factor=1.1)
 
@@ -117,7 +118,7 @@ _lock = threading.Lock()
 _lib = None
 
 
-def iid_haps_cfg(name: str = "cfg1") -> dict:
+def iid_haps_cfg(name: str = "batched_uneven") -> dict:
     """The stress variant of a workload: the same recipe with every haplotype
     drawn i.i.d. instead of as variants of one source haplotype, so that a
     read matches one haplotype of its region and most of its pairs fall far

@@ -21,8 +21,8 @@ import synth  # noqa: E402
 
 # (name, workload, first region): each region is one read x one haplotype
 CASES = [
-    ("long_read_100k", "cfg2", 64),
-    ("max_read_131072", dict(synth.CONFIGS["cfg2"], regions=1, n_len_classes=1,
+    ("long_read_100k", "long_reads", 64),
+    ("max_read_131072", dict(synth.CONFIGS["long_reads"], regions=1, n_len_classes=1,
                              len_classes=(131072, 0, 0, 0), regions_per_class=1,
                              hap_len_factor=1.1), 0),
 ]

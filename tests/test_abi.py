@@ -57,7 +57,7 @@ def test_default_options():
 
 
 def small_batch():
-    return synth.generate("cfg0")
+    return synth.generate("one_region")
 
 
 def expect(code, batch, match):

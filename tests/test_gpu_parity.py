@@ -68,19 +68,19 @@ def check(batch, got, flags, idx=None, tol32=TOL32, tol64=TOL64, plain64=False):
     return want, d
 
 
-def test_cfg0_fp64_plain(ctx64):
-    b = synth.generate("cfg0")
-    say("cfg0 fp64 plain: 512 pairs")
+def test_one_region_fp64_plain(ctx64):
+    b = synth.generate("one_region")
+    say("one_region fp64 plain: 512 pairs")
     out, fl = phmm.phmm_forward_batch(ctx64, b)
     want, d = check(b, out, fl, plain64=True)
     assert np.all(fl == phmm.PHMM_FLAG_FP64)
     say("  max |dlog10| = %.3g" % d.max())
 
 
-def test_cfg0_fp32_rerun_policy():
+def test_one_region_fp32_rerun_policy():
     # the one-region workload has i.i.d. haplotypes, which the packer would
     # send to FP64 directly; here every read starts in FP32
-    b = synth.generate("cfg0")
+    b = synth.generate("one_region")
     with phmm.Context(route_diverse_fp64=False) as c:
         out, fl = phmm.phmm_forward_batch(c, b)
     want, d = check(b, out, fl)
@@ -90,7 +90,7 @@ def test_cfg0_fp32_rerun_policy():
     # threshold (the error bound is checked above either way)
     assert not np.any(rerun[want > THRESH + 1e-3])
     assert np.all(rerun[want < THRESH - 200])
-    say("cfg0 fp32: rerun %d of %d, max err fp32 %.3g" % (rerun.sum(), len(out),
+    say("one_region fp32: rerun %d of %d, max err fp32 %.3g" % (rerun.sum(), len(out),
                                                           d[~rerun].max() if (~rerun).any() else 0))
 
 
@@ -99,14 +99,14 @@ def test_unrelated_haplotypes_start_in_fp64(ctx32):
     8 i.i.d. haplotypes) run in FP64 from the start: no pair is accepted in
     FP32 or rerun, and every result is within the FP64 bound.  Variant
     haplotypes of one locus (the batched workload) still start in FP32."""
-    b = synth.generate("cfg0")
+    b = synth.generate("one_region")
     out, fl = phmm.phmm_forward_batch(ctx32, b)
     check(b, out, fl, plain64=True)
     assert np.all(fl == phmm.PHMM_FLAG_FP64)
-    v = synth.generate("cfg1", 0, 30)
+    v = synth.generate("batched_uneven", 0, 30)
     out, fl = phmm.phmm_forward_batch(ctx32, v)
     assert ((fl & phmm.PHMM_FLAG_FP32) != 0).mean() > 0.99
-    iid = synth.generate(synth.iid_haps_cfg("cfg1"), 0, 30)
+    iid = synth.generate(synth.iid_haps_cfg("batched_uneven"), 0, 30)
     out, fl = phmm.phmm_forward_batch(ctx32, iid)
     n = len(iid["pair_list"])
     idx = np.arange(0, n, max(1, n // 300))
@@ -115,18 +115,18 @@ def test_unrelated_haplotypes_start_in_fp64(ctx32):
         % (int((fl == phmm.PHMM_FLAG_FP64).sum()), n))
 
 
-def test_cfg1_sample_fp32_rerun(ctx32):
-    b = synth.generate("cfg1", 0, 60)
+def test_batched_uneven_sample_fp32_rerun(ctx32):
+    b = synth.generate("batched_uneven", 0, 60)
     n = len(b["pair_list"])
-    say("cfg1 60 regions: %d pairs, %.3g cells" % (n, synth.batch_cells(b)))
+    say("batched_uneven 60 regions: %d pairs, %.3g cells" % (n, synth.batch_cells(b)))
     out, fl = phmm.phmm_forward_batch(ctx32, b)
     rng = np.random.default_rng(11)
     idx = np.sort(rng.choice(n, size=min(n, 1500), replace=False))
     check(b, out, fl, idx)
 
 
-def test_cfg3_sample_fp32_rerun(ctx32):
-    b = synth.generate("cfg3", 0, 40)
+def test_genome_scale_sample_fp32_rerun(ctx32):
+    b = synth.generate("genome_scale", 0, 40)
     n = len(b["pair_list"])
     out, fl = phmm.phmm_forward_batch(ctx32, b)
     rng = np.random.default_rng(12)
@@ -137,7 +137,7 @@ def test_cfg3_sample_fp32_rerun(ctx32):
 @pytest.mark.parametrize("cls", range(21))
 def test_every_class_fp32_and_fp64(cls):
     """Force each column class; pairs too long for it fall back to the widest."""
-    b = synth.generate("cfg1", 100, 6)
+    b = synth.generate("batched_uneven", 100, 6)
     n = len(b["pair_list"])
     idx = np.arange(0, n, max(1, n // 200))
     for prec in (phmm.PHMM_FP32_RERUN, phmm.PHMM_FP64_PLAIN):
@@ -150,7 +150,7 @@ def test_packing_position_only_changes_rounding():
     """A pair alone in its wavefront and packed beside others agrees to rounding
     (the scan's combine tree depends on the lane a segment starts at), and the
     same pack position always gives the same bits."""
-    b = synth.generate("cfg1", 7, 5)
+    b = synth.generate("batched_uneven", 7, 5)
     for cls in (2, 6, 10):
         with phmm.Context(force_class=cls) as c:
             packed, f1 = phmm.phmm_forward_batch(c, b)
@@ -166,7 +166,7 @@ def test_packing_position_only_changes_rounding():
 
 
 def test_deterministic(ctx32):
-    b = synth.generate("cfg1", 3, 8)
+    b = synth.generate("batched_uneven", 3, 8)
     a, fa = phmm.phmm_forward_batch(ctx32, b)
     c, fc = phmm.phmm_forward_batch(ctx32, b)
     assert np.array_equal(a.view(np.uint64), c.view(np.uint64)) and np.array_equal(fa, fc)
@@ -293,7 +293,7 @@ def test_scaled_row_form_limits(ctx32, ctx64):
 
 
 def test_unsorted_pairs_and_duplicates(ctx32):
-    b = synth.generate("cfg1", 11, 3)
+    b = synth.generate("batched_uneven", 11, 3)
     pl = b["pair_list"]
     rng = np.random.default_rng(3)
     perm = rng.permutation(len(pl))
@@ -377,8 +377,8 @@ def test_long_fp32_beyond_default_row_limit():
     """FP32 long pairs with dithered coefficient rounding, on reads of 10 and
     32 kbp (above the default FP32 row limit): the error against the oracle
     stays within the FP32 bound."""
-    b = synth.generate("cfg2", 0, 1)
-    b32 = synth.generate("cfg2", 32, 1)
+    b = synth.generate("long_reads", 0, 1)
+    b32 = synth.generate("long_reads", 32, 1)
     with phmm.Context(long_fp32_max_rows=200000) as c:
         for bb in (b, b32):
             out, fl = phmm.phmm_forward_batch(c, bb)
@@ -388,20 +388,20 @@ def test_long_fp32_beyond_default_row_limit():
                 (int(np.diff(bb["read_offsets"])[0]), out[0], want[0], d[0]))
 
 
-def test_cfg2_long_read_10k(ctx32):
-    b = synth.generate("cfg2", 0, 1)  # one 10 kbp read x 11 kbp haplotype
-    say("cfg2 region 0: read %d, hap %d" % (int(np.diff(b["read_offsets"])[0]),
+def test_long_reads_long_read_10k(ctx32):
+    b = synth.generate("long_reads", 0, 1)  # one 10 kbp read x 11 kbp haplotype
+    say("long_reads region 0: read %d, hap %d" % (int(np.diff(b["read_offsets"])[0]),
                                             int(np.diff(b["hap_offsets"])[0])))
     out, fl = phmm.phmm_forward_batch(ctx32, b)
     want, d = check(b, out, fl)
     say("  log10 L = %.6f (oracle %.6f)" % (out[0], want[0]))
 
 
-def test_cfg2_long_read_32k(ctx32):
-    b = synth.generate("cfg2", 32, 1)  # one 32 kbp read x 35.2 kbp haplotype (35 tiles)
+def test_long_reads_long_read_32k(ctx32):
+    b = synth.generate("long_reads", 32, 1)  # one 32 kbp read x 35.2 kbp haplotype (35 tiles)
     out, fl = phmm.phmm_forward_batch(ctx32, b)
     want, d = check(b, out, fl)
-    say("cfg2 region 32: log10 L = %.6f (oracle %.6f)" % (out[0], want[0]))
+    say("long_reads region 32: log10 L = %.6f (oracle %.6f)" % (out[0], want[0]))
 
 
 def _golden_long(name):
@@ -418,9 +418,9 @@ def test_longest_reads_against_stored_oracle(ctx32, name):
     tests/golden/make_long_reads.py (a minute or more of oracle time each)."""
     g = _golden_long(name)
     if name == "long_read_100k":
-        b = synth.generate("cfg2", g["region"], 1)
+        b = synth.generate("long_reads", g["region"], 1)
     else:
-        b = synth.generate(dict(synth.CONFIGS["cfg2"], regions=1, n_len_classes=1,
+        b = synth.generate(dict(synth.CONFIGS["long_reads"], regions=1, n_len_classes=1,
                                 len_classes=(131072, 0, 0, 0), regions_per_class=1,
                                 hap_len_factor=1.1), g["region"], 1)
     assert int(b["read_offsets"][1]) == g["read_len"] and int(b["hap_offsets"][1]) == g["hap_len"]
@@ -454,7 +454,7 @@ def test_async_matches_sync(ctx32):
     in the narrowest class that holds its longest haplotype, while the
     stream-ordered call follows the cost model, so the two agree to
     rounding."""
-    b = synth.generate("cfg1", 20, 10)
+    b = synth.generate("batched_uneven", 20, 10)
     with phmm.Context(force_class=8) as c:
         sync_out, sync_fl = phmm.phmm_forward_batch(c, b)
         a_out, a_fl, counts = _async_pass(c, b)
@@ -502,7 +502,7 @@ def test_chunked_sync_call_matches_async(ctx32):
     stream-ordered call's results, and a sample spread over both chunks
     matches the oracle."""
     import torch
-    b = synth.generate("cfg3", 0, 50000)
+    b = synth.generate("genome_scale", 0, 50000)
     n = len(b["pair_list"])
     assert n >= 2 * 2 * (1 << 22), n  # two chunks at least
     sync_out, sync_fl = phmm.phmm_forward_batch(ctx32, b)
@@ -557,7 +557,7 @@ def test_autotune_costs_and_results():
         assert np.all(costs > 0) and np.array_equal(costs, c.class_costs())
         # a wavefront-row of 24 columns costs more than one of 4
         assert costs[0][-1] > costs[0][0] and costs[1][-1] > costs[1][0]
-        b = synth.generate("cfg3", 7, 20)
+        b = synth.generate("genome_scale", 7, 20)
         out, fl = phmm.phmm_forward_batch(c, b)
         n = len(out)
         check(b, out, fl, np.arange(0, n, max(1, n // 400)))

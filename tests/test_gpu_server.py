@@ -31,7 +31,7 @@ def say(*a):
 def stream_regions():
     """A mixed stream: 160 regions of the served workload (short regions and
     long-read regions), cut short so the test stays quick."""
-    b = synth.generate("cfg4", 0, 160)
+    b = synth.generate("served_stream", 0, 160)
     regs = [synth.region_slice(b, i) for i in range(160)]
     nlong = sum(int(np.diff(r["read_offsets"]).max() > 2048 or
                     np.diff(r["hap_offsets"]).max() > 1536) for r in regs)
@@ -107,7 +107,7 @@ def test_served_short_regions_match_oracle(stream_regions):
 
 
 def test_poll_and_budget_limit():
-    b = synth.generate("cfg3", 0, 3)
+    b = synth.generate("genome_scale", 0, 3)
     r = synth.region_slice(b, 0)
     with phmm.Server(lanes=2, long_lanes=0, hbm_budget_bytes=512 << 20) as srv:
         t = srv.submit(r)

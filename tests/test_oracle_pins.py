@@ -210,7 +210,7 @@ def test_p7_rescaling_extends_range():
 
 # ---------------------------------------------------------------- P8
 def test_p8_bounds_and_true_path():
-    b = synth.generate("cfg0", with_cols=True)
+    b = synth.generate("one_region", with_cols=True)
     ro, ho = b["read_offsets"], b["hap_offsets"]
     pl = b["pair_list"]
     checked = 0
@@ -306,8 +306,8 @@ def test_p8_N_matches_anything():
     assert oracle.forward_one(b"AAA", *q, b"ANA")[0] == oracle.forward_one(b"AAA", *q, b"AAA")[0]
 
 
-def test_oracle_rescaled_matches_plain_on_cfg0():
-    b = synth.generate("cfg0")
+def test_oracle_rescaled_matches_plain_on_one_region():
+    b = synth.generate("one_region")
     idx = np.arange(0, 512, 5)
     plain = oracle.forward_pairs(b, idx, rescale=False)
     resc = oracle.forward_pairs(b, idx, rescale=True)
