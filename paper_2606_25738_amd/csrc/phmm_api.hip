@@ -951,7 +951,7 @@ extern "C" int phmm_autotune(phmm_ctx* c, uint64_t seed, float* out_costs)
             c->opt.one_pair_per_wave = 1;
             c->opt.timing = 1;
             float best = 0.f;
-            for (int rep = 0; rep < 5 && rc == PHMM_OK; ++rep) {  // best of 4 after a warm-up  // first run warms up
+            for (int rep = 0; rep < 3 && rc == PHMM_OK; ++rep) {  // first run warms up
                 rc = phmm_forward_batch(c, reads.data(), bq.data(), iq.data(), dq.data(), gq.data(),
                                         ro.data(), kReads, haps.data(), ho.data(), kHaps, pl.data(),
                                         n_pairs, out.data(), nullptr);
@@ -1005,27 +1005,26 @@ extern "C" int phmm_autotune_sample(phmm_ctx* c, const phmm_device_batch* sample
     if (hipMalloc(&out, (size_t)(sample->n_pairs ? sample->n_pairs : 1) * 9) != hipSuccess)
         rc = fail(PHMM_ENOMEM, "phmm_autotune_sample: output buffer");
     fl = reinterpret_cast<uint8_t*>(out + (sample->n_pairs ? sample->n_pairs : 1));
-    int best = 0;
-    float best_ms = 0.f;
     float saved[2][kNumClasses];
     memcpy(saved, c->cost, sizeof saved);
-    for (int k = 0; k < kCand && rc == PHMM_OK; ++k) {
-        memcpy(c->cost, cand[k], sizeof saved);
-        float t_best = 0.f;
-        for (int rep = 0; rep < 3 && rc == PHMM_OK; ++rep) {
+    // the candidates take turns (one pass each per round, a warm-up round
+    // first), so that a drift of the clock over the run favours none of them;
+    // each keeps its best time over the four timed rounds
+    float t_best[kCand] = {};
+    for (int rep = 0; rep < 5 && rc == PHMM_OK; ++rep)
+        for (int k = 0; k < kCand && rc == PHMM_OK; ++k) {
+            memcpy(c->cost, cand[k], sizeof saved);
             rc = phmm_forward_batch_async(c, sample, out, fl, d_ws, ws_bytes, s);
             if (rc != PHMM_OK) break;
             float ms = 0.f;
             if (hipEventSynchronize(c->ev[4]) != hipSuccess ||
                 hipEventElapsedTime(&ms, c->ev[0], c->ev[prec == 0 ? 2 : 3]) != hipSuccess)
                 rc = fail(PHMM_EDEVICE, "phmm_autotune_sample: event timing failed");
-            if (rep > 0 && (t_best == 0.f || ms < t_best)) t_best = ms;
+            if (rep > 0 && (t_best[k] == 0.f || ms < t_best[k])) t_best[k] = ms;
         }
-        if (rc == PHMM_OK && (k == 0 || t_best < best_ms)) {
-            best = k;
-            best_ms = t_best;
-        }
-    }
+    int best = 0;
+    for (int k = 1; k < kCand; ++k)
+        if (t_best[k] < t_best[best]) best = k;
     if (out) (void)hipFree(out);
     c->opt.timing = timing;
     memcpy(c->cost, rc == PHMM_OK ? cand[best] : saved, sizeof saved);
