@@ -609,6 +609,47 @@ def small_batch_leg(phmm, torch, args):
     return res
 
 
+def genotype_leg(phmm, torch, ctx, batch, out, stream, reps):
+    """Genotype likelihoods of every region of the step, straight on the
+    forward pass's device output (phmm_genotype_batch_async): kernel time
+    from HIP events on its stream, best of reps after a warm-up."""
+    rp, rr, rh = batch["region_pairs"], batch["region_reads"], batch["region_haps"]
+    R = np.diff(rr).astype(np.int64)
+    H = np.diff(rh).astype(np.int64)
+    go, n_gl = phmm.genotype_offsets(H)
+    dev = "cuda:0"
+    lo_d = torch.from_numpy(rp[:-1].astype(np.int64)).to(dev)
+    r_d = torch.from_numpy(R.astype(np.int32)).to(dev)
+    h_d = torch.from_numpy(H.astype(np.int32)).to(dev)
+    go_d = torch.from_numpy(go.astype(np.int64)).to(dev)
+    gl = torch.empty(n_gl, dtype=torch.float64, device=dev)
+    best = torch.empty(len(H), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    times = []
+    for r in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            phmm.phmm_genotype_batch_async(ctx, out, lo_d, r_d, h_d, go_d, gl, best, stream)
+            e1.record(stream)
+        e1.synchronize()
+        if r > 0:
+            times.append(e0.elapsed_time(e1))
+    ms = min(times)
+    G = H * (H + 1) // 2
+    terms = int((G * R).sum())
+    het = int(((G - H) * R).sum())
+    nbytes = 8 * int((R * H).sum()) + 8 * n_gl + 4 * len(H) + 24 * len(H)
+    log("genotype likelihoods: %d regions, %.3g read terms (%.3g heterozygous) in %.3f ms"
+        % (len(H), terms, het, ms))
+    return dict(ms=round(ms, 3), regions=len(H), genotypes=n_gl, read_terms=terms,
+                het_read_terms=het, g_terms_per_s=round(terms / (ms * 1e-3) / 1e9, 2),
+                gb_per_s=round(nbytes / (ms * 1e-3) / 1e9, 1),
+                note="diploid genotype log10-likelihoods of every region from the step's "
+                     "log10 P(read|hap) on the device; FP64, two transcendentals per "
+                     "heterozygous read term")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -628,6 +669,9 @@ def main():
     ap.add_argument("--uneven", type=int, default=1,
                     help="run the batched uneven short-pair workload and its i.i.d. stress "
                          "variant (0 = skip)")
+    ap.add_argument("--genotype-reps", type=int, default=3,
+                    help="timed runs of the genotype-likelihood kernel on the step's output "
+                         "(0 skips it)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default pack cost model instead of measuring it")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -804,6 +848,11 @@ def main():
                     speedup_fp32_rerun=round(value / (cells / (e64 / args.fp64_steps) / 1e9), 3))
         ctx64.close()
 
+    genotype = None
+    if args.genotype_reps > 0:
+        genotype = genotype_leg(phmm, torch, ctx, batch, out, stream, args.genotype_reps)
+        genotype["share_of_step"] = round(genotype["ms"] / ms_per_step, 5)
+
     end_to_end = None
     if args.end_to_end:
         # host arrays in, host results out (synchronous API): copies, device
@@ -859,6 +908,7 @@ def main():
                                                    fp64=np.round(costs[1], 3).tolist()),
         fp64_plain=fp64, fp64_one_pair_per_wave=opw, end_to_end=end_to_end,
         batched_uneven=uneven, small_batch=small, parity_sample=parity, serving=serving,
+        genotype_likelihoods=genotype,
     )
     print(json.dumps(rec), flush=True)
 

@@ -292,6 +292,60 @@ int phmm_autotune_sample(phmm_ctx* ctx, const phmm_device_batch* sample, void* d
 int phmm_set_class_costs(phmm_ctx* ctx, const float* costs);
 int phmm_get_class_costs(phmm_ctx* ctx, float* costs);
 
+/*
+ * Genotype likelihoods (the Bayesian genotyping step that follows the
+ * PairHMM, Section 1): for each active region, the diploid genotype
+ * log-likelihoods from its read x haplotype matrix of log10 P(read | hap).
+ *
+ * Region g has region_reads[g] = R reads and region_haps[g] = H haplotypes
+ * (1 <= H <= PHMM_GT_MAX_HAPS, R may be 0); its matrix is the R x H doubles
+ * lk[lk_offsets[g] + r*H + h] (read-major: the order of the pairs a region's
+ * reads and haplotypes give in pair_list when each read lists its
+ * haplotypes in turn).  For each genotype a <= b the call writes
+ *
+ *   gl[gl_offsets[g] + b(b+1)/2 + a] = sum_r log10(10^lk[r][a]/2 + 10^lk[r][b]/2)
+ *
+ * (each read drawn from either haplotype copy with probability 1/2; the
+ * genotype order is the VCF one for ploidy 2) and best[g] = the index of the
+ * largest of them, the smallest index on ties (the maximum a posteriori
+ * genotype under a flat prior).  A region with R = 0 has every entry 0 and
+ * best 0.  Each term is evaluated as max + log10(1 + 10^-|diff|) - log10 2 in
+ * FP64, so no likelihood underflows; results agree with the plain sum within
+ * 1e-12 relative.
+ *
+ * Host form: every array is a host buffer; lk holds n_lk doubles and gl n_gl.
+ * The host checks, before any device work, that each region's matrix lies in
+ * [0, n_lk), that its H(H+1)/2 genotypes lie in [0, n_gl), that H is in
+ * range and that every lk value the regions use is finite; on error nothing
+ * is written and phmm_last_error() names the first offending region or
+ * index.  Genotype blocks of different regions must not overlap (not
+ * checked: overlapping blocks give unspecified values).  Arguments are checked
+ * before the context, so a NULL ctx reports input errors first.
+ * Errors: PHMM_EINVAL, PHMM_ENOMEM, PHMM_EDEVICE.
+ */
+#define PHMM_GT_MAX_HAPS 1024u
+int phmm_genotype_batch(phmm_ctx* ctx, const double* lk, uint64_t n_lk,
+                        const uint64_t* lk_offsets, const uint32_t* region_reads,
+                        const uint32_t* region_haps, const uint64_t* gl_offsets,
+                        uint32_t n_regions, double* gl, uint64_t n_gl, uint32_t* best);
+
+/*
+ * Stream-ordered form: the same arrays as device pointers, enqueued on
+ * hip_stream (a hipStream_t, NULL = null stream) without synchronisation or
+ * allocation, e.g. straight on the d_out_log10 of phmm_forward_batch_async.
+ * Device contents are not checked on the host; the kernel itself skips a
+ * region whose matrix or genotype block does not lie within n_lk / n_gl or
+ * whose H is 0 or above PHMM_GT_MAX_HAPS, and sets its best to 0xFFFFFFFF
+ * (nothing else of it is written).  Non-finite likelihoods give non-finite
+ * results.  Errors: PHMM_EINVAL (NULL ctx, NULL array with n_regions > 0),
+ * PHMM_EDEVICE (launch failure).
+ */
+int phmm_genotype_batch_async(phmm_ctx* ctx, const double* d_lk, uint64_t n_lk,
+                              const uint64_t* d_lk_offsets, const uint32_t* d_region_reads,
+                              const uint32_t* d_region_haps, const uint64_t* d_gl_offsets,
+                              uint32_t n_regions, double* d_gl, uint64_t n_gl,
+                              uint32_t* d_best, void* hip_stream);
+
 /* Calibration: measures the device's achievable vector FMA rates (FP32
  * scalar FMA and FP64 FMA, TFLOP/s with an FMA counted as two flops) with
  * independent FMA chains in every lane.  Used to state the ALU roofline the

@@ -14,8 +14,12 @@ Contents
 ``exact.py``
     pure-Python path enumeration and exact rational evaluation, used only to
     pin the C oracle on tiny inputs.
+``genotype.py``
+    diploid genotype likelihoods from a read x haplotype likelihood matrix
+    (the genotyping step after the PairHMM), plain FP64 definition.
 """
 from .oracle import (  # noqa: F401
     NREC, build_oracle, priors, forward_probs, forward_one, forward_pairs,
     forward_antidiag_probs, forward_rowform_probs, lib_path,
 )
+from .genotype import genotype_region, genotype_batch, best_genotype  # noqa: F401

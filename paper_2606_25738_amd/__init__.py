@@ -12,4 +12,5 @@ from ._binding import (  # noqa: F401
     phmm_num_classes, phmm_class_n, phmm_validate_batch, phmm_forward_batch,
     phmm_forward_one, phmm_workspace_bytes, phmm_forward_batch_async, phmm_device_status,
     phmm_last_counts, phmm_last_timing, phmm_vector_peak, phmm_copy_calib, DeviceBatch,
+    genotype_offsets, phmm_genotype_batch, phmm_genotype_batch_async,
 )

@@ -138,6 +138,11 @@ def lib():
             L.phmm_autotune_sample.argtypes = [vp, ctypes.POINTER(_DeviceBatch), vp, ctypes.c_size_t,
                                                vp, fp]
             L.phmm_get_class_costs.argtypes = [vp, fp]
+            L.phmm_genotype_batch.argtypes = [vp, dp, ctypes.c_uint64, u64p, u32p, u32p, u64p,
+                                              ctypes.c_uint32, dp, ctypes.c_uint64, u32p]
+            L.phmm_genotype_batch_async.argtypes = [vp] + [ctypes.c_void_p, ctypes.c_uint64] + \
+                [ctypes.c_void_p] * 4 + [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64,
+                                         ctypes.c_void_p, ctypes.c_void_p]
             L.phmm_server_default_options.argtypes = [ctypes.POINTER(_ServerOptions)]
             L.phmm_server_default_options.restype = None
             L.phmm_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int,
@@ -363,6 +368,55 @@ def phmm_forward_batch_async(ctx: Context, db: DeviceBatch, out, flags, workspac
         ctx.handle, ctypes.byref(s), out.data_ptr(),
         flags.data_ptr() if flags is not None else None, workspace.data_ptr(),
         workspace.numel() * workspace.element_size(), h))
+
+
+def genotype_offsets(region_haps) -> tuple[np.ndarray, int]:
+    """Back-to-back genotype blocks: the offset of each region's H(H+1)/2
+    genotypes and their total."""
+    h = np.asarray(region_haps, dtype=np.uint64)
+    g = h * (h + np.uint64(1)) // np.uint64(2)
+    off = np.zeros(len(h), np.uint64)
+    if len(h) > 1:
+        off[1:] = np.cumsum(g[:-1], dtype=np.uint64)
+    return off, int(g.sum()) if len(h) else 0
+
+
+def phmm_genotype_batch(ctx: Context | None, lk, lk_offsets, region_reads, region_haps,
+                        gl_offsets=None, gl=None):
+    """Diploid genotype log10-likelihoods per region from the read x haplotype
+    log10 matrix (host arrays) -> (gl, best).  gl_offsets None: back-to-back
+    blocks; gl None: a new array of the needed size.  ctx None only exercises
+    the host-side checks (a valid batch then fails with PHMM_EINVAL)."""
+    lk = np.ascontiguousarray(lk, dtype=np.float64)
+    lo, lo_p = _u64(lk_offsets)
+    nr, nr_p = _u32(region_reads)
+    nh, nh_p = _u32(region_haps)
+    if gl_offsets is None:
+        gl_offsets, n_gl = genotype_offsets(nh)
+    else:
+        n_gl = None
+    go, go_p = _u64(gl_offsets)
+    if gl is None:
+        gl = np.zeros(n_gl if n_gl is not None else 0, np.float64)
+    gl = np.ascontiguousarray(gl, dtype=np.float64)
+    best = np.zeros(len(nh), np.uint32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().phmm_genotype_batch(ctx.handle if ctx is not None else None,
+                                     lk.ctypes.data_as(dp), lk.size, lo_p, nr_p, nh_p, go_p,
+                                     len(nh), gl.ctypes.data_as(dp), gl.size,
+                                     best.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+    return gl, best
+
+
+def phmm_genotype_batch_async(ctx: Context, lk, lk_offsets, region_reads, region_haps,
+                              gl_offsets, gl, best, stream=None):
+    """Stream-ordered genotype likelihoods on device tensors (float64 lk and
+    gl, int64 offsets, int32 counts and best)."""
+    h = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    _check(lib().phmm_genotype_batch_async(
+        ctx.handle, lk.data_ptr(), lk.numel(), lk_offsets.data_ptr(), region_reads.data_ptr(),
+        region_haps.data_ptr(), gl_offsets.data_ptr(), region_haps.numel(), gl.data_ptr(),
+        gl.numel(), best.data_ptr(), h))
 
 
 def phmm_device_status(ctx: Context, workspace):

@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libphmm.so")
 SOURCES = ["phmm_api.hip", "phmm_pack.hip", "phmm_short.hip", "phmm_long.hip", "phmm_peak.hip",
-           "phmm_server.hip"]
+           "phmm_server.hip", "phmm_genotype.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

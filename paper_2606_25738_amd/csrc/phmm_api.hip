@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -26,6 +27,10 @@ uint32_t scan_chunks(uint32_t n_pack_blocks);
 void launch_long(hipStream_t s, const int (&grid)[2], const Batch& b, const Tables& t,
                  const Work& w, const Policy& p);
 const void* long_kernel_ptr(bool fp32);
+int launch_genotype(hipStream_t s, int cus, const double* lk, uint64_t n_lk,
+                    const uint64_t* lk_off, const uint32_t* n_reads, const uint32_t* n_haps,
+                    const uint64_t* gl_off, uint32_t n_regions, double* gl, uint64_t n_gl,
+                    uint32_t* best);
 __host__ __device__ uint32_t long_slots(int grid);
 size_t long_ring_slot_bytes();
 }  // namespace phmm
@@ -849,6 +854,92 @@ extern "C" int phmm_forward_batch(phmm_ctx* c, const uint8_t* reads, const uint8
 }
 
 static std::mutex g_default_mu;
+// ---------------------------------------------------------------- genotypes
+static int genotype_args(const void* lk, const uint64_t* lo, const uint32_t* nr,
+                         const uint32_t* nh, const uint64_t* go, uint32_t n_regions,
+                         const void* gl, const uint32_t* best)
+{
+    if (n_regions == 0) return PHMM_OK;
+    if (!lk || !lo || !nr || !nh || !go || !gl || !best)
+        return fail(PHMM_EINVAL, "genotype batch: NULL array with %u regions", n_regions);
+    return PHMM_OK;
+}
+
+extern "C" int phmm_genotype_batch(phmm_ctx* c, const double* lk, uint64_t n_lk,
+                                   const uint64_t* lo, const uint32_t* nr, const uint32_t* nh,
+                                   const uint64_t* go, uint32_t n_regions, double* gl,
+                                   uint64_t n_gl, uint32_t* best)
+{
+    int rc = genotype_args(lk, lo, nr, nh, go, n_regions, gl, best);
+    if (rc != PHMM_OK) return rc;
+    for (uint32_t g = 0; g < n_regions; ++g) {
+        const uint64_t R = nr[g], H = nh[g], G = H * (H + 1) / 2;
+        if (H == 0 || H > PHMM_GT_MAX_HAPS)
+            return fail(PHMM_EINVAL, "region %u: %llu haplotypes (1..%u allowed)", g,
+                        (unsigned long long)H, PHMM_GT_MAX_HAPS);
+        if (lo[g] > n_lk || R * H > n_lk - lo[g])
+            return fail(PHMM_EINVAL, "region %u: likelihoods [%llu, +%llu) outside n_lk = %llu",
+                        g, (unsigned long long)lo[g], (unsigned long long)(R * H),
+                        (unsigned long long)n_lk);
+        if (go[g] > n_gl || G > n_gl - go[g])
+            return fail(PHMM_EINVAL, "region %u: genotypes [%llu, +%llu) outside n_gl = %llu",
+                        g, (unsigned long long)go[g], (unsigned long long)G,
+                        (unsigned long long)n_gl);
+        for (uint64_t t = 0; t < R * H; ++t)
+            if (!std::isfinite(lk[lo[g] + t]))
+                return fail(PHMM_EINVAL, "region %u: lk[%llu] is not finite", g,
+                            (unsigned long long)(lo[g] + t));
+    }
+    if (!c) return fail(PHMM_EINVAL, "phmm_genotype_batch: NULL ctx");
+    if (n_regions == 0) return PHMM_OK;
+    HIP_TRY(hipSetDevice(c->device));
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t b_lk = up(n_lk * 8), b_gl = up(n_gl * 8), b_r8 = up((size_t)n_regions * 8),
+                 b_r4 = up((size_t)n_regions * 4);
+    rc = ensure_arena(c, b_lk + b_gl + 2 * b_r8 + 3 * b_r4);
+    if (rc != PHMM_OK) return rc;
+    char* p = static_cast<char*>(c->arena);
+    double* d_lk = reinterpret_cast<double*>(p);
+    double* d_gl = reinterpret_cast<double*>(p += b_lk);
+    uint64_t* d_lo = reinterpret_cast<uint64_t*>(p += b_gl);
+    uint64_t* d_go = reinterpret_cast<uint64_t*>(p += b_r8);
+    uint32_t* d_nr = reinterpret_cast<uint32_t*>(p += b_r8);
+    uint32_t* d_nh = reinterpret_cast<uint32_t*>(p += b_r4);
+    uint32_t* d_best = reinterpret_cast<uint32_t*>(p += b_r4);
+    hipStream_t s = c->stream;
+    HIP_TRY(hipMemcpyAsync(d_lk, lk, n_lk * 8, hipMemcpyHostToDevice, s));
+    // entries of gl outside every region's block keep the caller's values
+    HIP_TRY(hipMemcpyAsync(d_gl, gl, n_gl * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_lo, lo, (size_t)n_regions * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_go, go, (size_t)n_regions * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_nr, nr, (size_t)n_regions * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_nh, nh, (size_t)n_regions * 4, hipMemcpyHostToDevice, s));
+    if (launch_genotype(s, c->cus, d_lk, n_lk, d_lo, d_nr, d_nh, d_go, n_regions, d_gl, n_gl,
+                        d_best) != 0)
+        return fail(PHMM_EDEVICE, "genotype kernel launch failed");
+    HIP_TRY(hipMemcpyAsync(gl, d_gl, n_gl * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(best, d_best, (size_t)n_regions * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PHMM_OK;
+}
+
+extern "C" int phmm_genotype_batch_async(phmm_ctx* c, const double* d_lk, uint64_t n_lk,
+                                         const uint64_t* d_lo, const uint32_t* d_nr,
+                                         const uint32_t* d_nh, const uint64_t* d_go,
+                                         uint32_t n_regions, double* d_gl, uint64_t n_gl,
+                                         uint32_t* d_best, void* hip_stream)
+{
+    if (!c) return fail(PHMM_EINVAL, "phmm_genotype_batch_async: NULL ctx");
+    const int rc = genotype_args(d_lk, d_lo, d_nr, d_nh, d_go, n_regions, d_gl, d_best);
+    if (rc != PHMM_OK) return rc;
+    if (n_regions == 0) return PHMM_OK;
+    HIP_TRY(hipSetDevice(c->device));
+    if (launch_genotype(static_cast<hipStream_t>(hip_stream), c->cus, d_lk, n_lk, d_lo, d_nr,
+                        d_nh, d_go, n_regions, d_gl, n_gl, d_best) != 0)
+        return fail(PHMM_EDEVICE, "genotype kernel launch failed");
+    return PHMM_OK;
+}
+
 static phmm_ctx* g_default = nullptr;
 
 extern "C" int phmm_forward_one(const uint8_t* read, const uint8_t* bq, const uint8_t* iq,

@@ -1,0 +1,135 @@
+// Diploid genotype likelihoods from the read x haplotype likelihood matrix of
+// an active region: the Bayesian genotyping stage that consumes the PairHMM
+// output (Section 1 names it as the step after the PairHMM).
+//
+// For a region with R reads, H haplotypes and L[r][h] = log10 P(read r | hap h),
+// the genotype made of haplotypes a <= b (a diploid sample: each read comes
+// from either copy with probability 1/2) has
+//
+//   GL(a,b) = sum_r log10( P(r|a)/2 + P(r|b)/2 ),
+//
+// stored at index b(b+1)/2 + a of the region's genotype block (the genotype
+// order of the VCF format for ploidy 2).  Each term is taken as
+//
+//   max(La,Lb) + log10(1 + 10^-|La-Lb|) - log10 2     (a != b),   La   (a == b),
+//
+// which never leaves the FP64 range whatever the likelihoods (they reach
+// -3e4 for long reads).  best = argmax GL, the smallest index on ties: the
+// maximum a posteriori genotype under a flat prior.
+//
+// Work mapping: one wavefront per region (grid-stride over regions).  The
+// region's matrix is staged in LDS in chunks of whole reads; lane t owns the
+// genotypes t, t + 64, ...; the arithmetic is FP64 (two transcendentals per
+// heterozygous genotype and read), so the kernel is bound by the FP64 VALU.
+#include <math.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include <hip/hip_runtime.h>
+
+#include "phmm.h"
+
+namespace phmm {
+
+constexpr int kGtLane = 64;
+constexpr uint32_t kGtLds = 1024;  // doubles of the matrix staged per chunk
+
+// b = the largest integer with b(b+1)/2 <= g, a = g - b(b+1)/2.
+__device__ inline void genotype_pair(uint32_t g, uint32_t& a, uint32_t& b)
+{
+    uint32_t t = (uint32_t)((sqrt(8.0 * (double)g + 1.0) - 1.0) * 0.5);
+    while ((uint64_t)(t + 1) * (t + 2) / 2 <= g) ++t;
+    while ((uint64_t)t * (t + 1) / 2 > g) --t;
+    b = t;
+    a = g - t * (t + 1) / 2;
+}
+
+__device__ inline double het_term(double la, double lb)
+{
+    const double m = fmax(la, lb);
+    const double d = fabs(la - lb);
+    return m + log1p(exp10(-d)) * 0.43429448190325182765 - 0.30102999566398119521;
+}
+
+__global__ __launch_bounds__(kGtLane) void genotype_kernel(
+    const double* __restrict__ lk, uint64_t n_lk, const uint64_t* __restrict__ lk_off,
+    const uint32_t* __restrict__ n_reads, const uint32_t* __restrict__ n_haps,
+    const uint64_t* __restrict__ gl_off, uint32_t n_regions, double* __restrict__ gl,
+    uint64_t n_gl, uint32_t* __restrict__ best)
+{
+    __shared__ double s_lk[kGtLds];
+    const uint32_t lane = threadIdx.x;
+    for (uint32_t reg = blockIdx.x; reg < n_regions; reg += gridDim.x) {
+        const uint64_t lo = lk_off[reg];
+        const uint64_t go = gl_off[reg];
+        const uint32_t R = n_reads[reg];
+        const uint32_t H = n_haps[reg];
+        const uint64_t G = (uint64_t)H * (H + 1) / 2;
+        const bool ok = H >= 1 && H <= PHMM_GT_MAX_HAPS && lo <= n_lk &&
+                        (uint64_t)R * H <= n_lk - lo && go <= n_gl && G <= n_gl - go;
+        if (!ok) {  // block outside the arrays: nothing read or written but best
+            if (lane == 0) best[reg] = 0xFFFFFFFFu;
+            continue;
+        }
+        const uint32_t rchunk = kGtLds / H;  // >= 1 since H <= PHMM_GT_MAX_HAPS <= kGtLds
+        uint32_t staged_r0 = 0xFFFFFFFFu;     // first read of the chunk in LDS
+        double bv = -INFINITY;
+        uint32_t bi = 0xFFFFFFFFu;
+        for (uint64_t g0 = 0; g0 < G; g0 += kGtLane) {
+            const uint64_t gi = g0 + lane;
+            const bool act = gi < G;
+            uint32_t a = 0, b = 0;
+            if (act) genotype_pair((uint32_t)gi, a, b);
+            double acc = 0.0;
+            for (uint32_t r0 = 0; r0 < R; r0 += rchunk) {
+                const uint32_t rn = min(rchunk, R - r0);
+                if (staged_r0 != r0) {
+                    __syncthreads();
+                    const double* src = lk + lo + (uint64_t)r0 * H;
+                    for (uint32_t t = lane; t < rn * H; t += kGtLane) s_lk[t] = src[t];
+                    __syncthreads();
+                    staged_r0 = r0;
+                }
+                if (act) {
+                    if (a == b)
+                        for (uint32_t r = 0; r < rn; ++r) acc += s_lk[r * H + a];
+                    else
+                        for (uint32_t r = 0; r < rn; ++r)
+                            acc += het_term(s_lk[r * H + a], s_lk[r * H + b]);
+                }
+            }
+            if (act) {
+                gl[go + gi] = acc;
+                if (acc > bv) {
+                    bv = acc;
+                    bi = (uint32_t)gi;
+                }
+            }
+        }
+        // wavefront argmax: larger value, then smaller index
+        for (int off = kGtLane / 2; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(bv, off, kGtLane);
+            const uint32_t oi = __shfl_xor(bi, off, kGtLane);
+            if (ov > bv || (ov == bv && oi < bi)) {
+                bv = ov;
+                bi = oi;
+            }
+        }
+        if (lane == 0) best[reg] = bi;
+    }
+}
+
+int launch_genotype(hipStream_t s, int cus, const double* lk, uint64_t n_lk,
+                    const uint64_t* lk_off, const uint32_t* n_reads, const uint32_t* n_haps,
+                    const uint64_t* gl_off, uint32_t n_regions, double* gl, uint64_t n_gl,
+                    uint32_t* best)
+{
+    if (n_regions == 0) return 0;
+    const uint32_t grid = std::min<uint32_t>(n_regions, (uint32_t)std::max(cus, 1) * 64u);
+    hipLaunchKernelGGL(genotype_kernel, dim3(grid), dim3(kGtLane), 0, s, lk, n_lk, lk_off,
+                       n_reads, n_haps, gl_off, n_regions, gl, n_gl, best);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace phmm

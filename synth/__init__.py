@@ -283,3 +283,40 @@ def region_slice(batch: dict, i: int) -> dict:
     pl = batch["pair_list"][int(rp[i]):int(rp[i + 1])].astype(np.int64)
     out["pair_list"] = np.stack([pl[:, 0] - r0, pl[:, 1] - h0], axis=1).astype(np.uint32)
     return out
+
+
+def genotype_lk(seed: int, n_regions: int, reads=(0, 60), haps=(1, 16), long_frac: float = 0.0):
+    """Synthetic read x haplotype log10-likelihood matrices shaped like the
+    PairHMM output of active regions (the input of the genotyping step).
+
+    Per region: R reads (uniform in [reads[0], reads[1]]) and H haplotypes
+    (uniform in [haps[0], haps[1]]).  Per read, one haplotype it was drawn
+    from scores -U(1, 25) (150 bp reads with sequencing errors); the others
+    trail it by Exp(mean 8) (a few mismatching bases), 10% of them by
+    U(50, 400) (an unrelated haplotype).  A long_frac share of the regions
+    has long-read values (-U(1e3, 3e4) for the best haplotype).
+
+    Returns (lk float64, lk_offsets uint64, region_reads uint32, region_haps
+    uint32) with the regions' R x H blocks back to back, read-major."""
+    g = np.random.default_rng(np.random.PCG64(seed))
+    R = g.integers(reads[0], reads[1] + 1, n_regions).astype(np.uint32)
+    H = g.integers(haps[0], haps[1] + 1, n_regions).astype(np.uint32)
+    sizes = R.astype(np.int64) * H.astype(np.int64)
+    off = np.zeros(n_regions, np.uint64)
+    if n_regions > 1:
+        off[1:] = np.cumsum(sizes[:-1]).astype(np.uint64)
+    n = int(sizes.sum())
+    lk = np.empty(n, np.float64)
+    longr = g.random(n_regions) < long_frac
+    for i in range(n_regions):
+        r, h = int(R[i]), int(H[i])
+        if r == 0:
+            continue
+        top = -(g.uniform(1e3, 3e4, r) if longr[i] else g.uniform(1.0, 25.0, r))
+        gap = g.exponential(8.0, (r, h))
+        far = g.random((r, h)) < 0.1
+        gap[far] = g.uniform(50.0, 400.0, int(far.sum()))
+        gap[np.arange(r), g.integers(0, h, r)] = 0.0
+        o = int(off[i])
+        lk[o:o + r * h] = (top[:, None] - gap).ravel()
+    return lk, off, R, H
