@@ -646,8 +646,8 @@ def genotype_leg(phmm, torch, ctx, batch, out, stream, reps):
                 het_read_terms=het, g_terms_per_s=round(terms / (ms * 1e-3) / 1e9, 2),
                 gb_per_s=round(nbytes / (ms * 1e-3) / 1e9, 1),
                 note="diploid genotype log10-likelihoods of every region from the step's "
-                     "log10 P(read|hap) on the device; FP64, two transcendentals per "
-                     "heterozygous read term")
+                     "log10 P(read|hap) on the device; FP64: a power per read and haplotype, "
+                     "a multiply and frexp per read and genotype, a logarithm per genotype")
 
 
 def main():

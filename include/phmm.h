@@ -309,9 +309,9 @@ int phmm_get_class_costs(phmm_ctx* ctx, float* costs);
  * genotype order is the VCF one for ploidy 2) and best[g] = the index of the
  * largest of them, the smallest index on ties (the maximum a posteriori
  * genotype under a flat prior).  A region with R = 0 has every entry 0 and
- * best 0.  Each term is evaluated as max + log10(1 + 10^-|diff|) - log10 2 in
- * FP64, so no likelihood underflows; results agree with the plain sum within
- * 1e-12 relative.
+ * best 0.  Each term is evaluated in FP64 relative to the read's largest
+ * likelihood, so no likelihood underflows; results agree with the plain sum
+ * within 1e-12 relative (the reads of a region may be summed in any order).
  *
  * Host form: every array is a host buffer; lk holds n_lk doubles and gl n_gl.
  * The host checks, before any device work, that each region's matrix lies in
@@ -323,7 +323,7 @@ int phmm_get_class_costs(phmm_ctx* ctx, float* costs);
  * before the context, so a NULL ctx reports input errors first.
  * Errors: PHMM_EINVAL, PHMM_ENOMEM, PHMM_EDEVICE.
  */
-#define PHMM_GT_MAX_HAPS 1024u
+#define PHMM_GT_MAX_HAPS 512u
 int phmm_genotype_batch(phmm_ctx* ctx, const double* lk, uint64_t n_lk,
                         const uint64_t* lk_offsets, const uint32_t* region_reads,
                         const uint32_t* region_haps, const uint64_t* gl_offsets,

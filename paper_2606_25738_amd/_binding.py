@@ -102,6 +102,15 @@ def lib():
         if _lib is None:
             if not os.path.exists(_LIB_PATH):
                 raise RuntimeError("libphmm.so is not built (python -m paper_2606_25738_amd.build)")
+            # torch ships its own HIP runtime under the same soname
+            # (libamdhip64.so.7) as the system one libphmm.so links: whichever
+            # is loaded first serves the whole process, and torch does not
+            # find the GPU on a runtime other than its own.  Load torch's
+            # first so that the library and torch share it.
+            try:
+                import torch  # noqa: F401
+            except ImportError:
+                pass
             L = ctypes.CDLL(_LIB_PATH)
             vp, u8p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint8)
             u64p, u32p = ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32)

@@ -151,7 +151,7 @@ def test_library_checks_inputs_before_the_context():
     lk = -np.arange(12, dtype=np.float64)
     _expect("NULL ctx", lk, [0, 6], [2, 1], [3, 6])
     _expect("region 1: 0 haplotypes", lk, [0, 6], [2, 1], [3, 0])
-    _expect("region 0: 1025 haplotypes", lk, [0], [0], [1025])
+    _expect("region 0: 513 haplotypes", lk, [0], [0], [513])
     _expect("region 1: likelihoods [6, +8)", lk, [0, 6], [2, 2], [3, 4])
     _expect("region 0: genotypes [5, +6)", lk, [0], [2], [3], gl_offsets=[5], gl=np.zeros(10))
     bad = lk.copy()
