@@ -609,6 +609,29 @@ def small_batch_leg(phmm, torch, args):
     return res
 
 
+def cpu_rowform_leg(batch, sidx, scells, ovals, cores):
+    """The CPU comparator (row-level formulation, SIMD rows, threads over
+    pairs) on the oracle's sample: best of two runs, error against the
+    oracle."""
+    import cpu_rowform
+    walls = []
+    for _ in range(2):
+        t = time.perf_counter()
+        vals, flags = cpu_rowform.forward_pairs(batch, sidx, threads=cores)
+        walls.append(time.perf_counter() - t)
+    wall = min(walls)
+    fin = np.isfinite(ovals)
+    d = np.abs(np.where(fin, vals, 0.0) - np.where(fin, ovals, 0.0))
+    res = dict(value=round(scells / wall / 1e9, 3), unit="GCUPS", cores=cores,
+               kind="row-level formulation on the host (AVX2 rows, OpenMP over pairs, FP32 "
+                    "with FP64 rerun)", seconds=round(wall, 3),
+               fp64_pairs=int((flags == 2).sum()),
+               max_err_fp32=float(d[flags == 1].max(initial=0.0)),
+               max_err_fp64=float(d[flags == 2].max(initial=0.0)))
+    log("CPU row-form comparator: %.3f GCUPS on %d threads" % (res["value"], cores))
+    return res
+
+
 def genotype_leg(phmm, torch, ctx, batch, out, stream, reps):
     """Genotype likelihoods of every region of the step, straight on the
     forward pass's device output (phmm_genotype_batch_async): kernel time
@@ -749,6 +772,7 @@ def main():
     # oracle sample first: worker processes fork before the GPU is touched
     cores = min(16, os.cpu_count() or 1)
     cpu = None
+    rowform = None
     if not args.no_cpu and args.cpu_regions > 0:
         sidx, nreg = sample_pairs(batch, args.cpu_regions)
         scells = int(cells_pp[sidx].sum())
@@ -761,6 +785,7 @@ def main():
                                                        scells / cpusec / 1e9),
                    seconds=round(wall, 2))
         log("oracle %.1fs wall, %.3f GCUPS on %d processes" % (wall, cpu["value"], cores))
+        rowform = cpu_rowform_leg(batch, sidx, scells, ovals, cores)
 
     import torch
     import paper_2606_25738_amd as phmm
@@ -900,7 +925,7 @@ def main():
                              "2-16 variant haplotypes of 150-600 bp, lognormal(mean 40, sigma 1) "
                              "reads per region, Phred 2-41; FP32 with FP64 rerun" % args.regions,
                     regions=args.regions, pairs=n_pairs, cells=cells),
-        roofline=roof, cpu_baseline=cpu,
+        roofline=roof, cpu_baseline=cpu, cpu_rowform=rowform,
         phases_ms={k: round(v, 3) for k, v in ph.items()},
         rerun_pairs=int(counts["rerun_pairs"]), rerun_fraction=counts["rerun_pairs"] / max(1, n_pairs),
         lane_utilisation=round(cells32 / max(1, counts["lane_columns"] * 150), 4),
