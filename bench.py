@@ -69,12 +69,41 @@ def _cpu_model():
     return None
 
 
+def sample_regions(batch, n_regions, seed=123):
+    nreg = len(batch["region_pairs"]) - 1
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(nreg, size=min(n_regions, nreg), replace=False))
+
+
 def sample_pairs(batch, n_regions, seed=123):
     rp = batch["region_pairs"]
-    nreg = len(rp) - 1
-    rng = np.random.default_rng(seed)
-    regs = np.sort(rng.choice(nreg, size=min(n_regions, nreg), replace=False))
+    regs = sample_regions(batch, n_regions, seed)
     return np.concatenate([np.arange(rp[r], rp[r + 1]) for r in regs]).astype(np.int64), len(regs)
+
+
+def genotype_parity(batch, n_regions, ovals, gl, n_check=300):
+    """Genotype likelihoods of the first n_check regions of the oracle's
+    sample: the oracle's genotyping of the oracle's forward values against
+    the GPU's genotyping of the GPU's forward output (gl, host copy).  Each
+    read's term moves by at most its likelihoods' error, so the tolerance is
+    1e-4 per read (the FP32 bound) plus 1e-12 relative."""
+    import oracle
+    import paper_2606_25738_amd as phmm
+    rr, rh = batch["region_reads"], batch["region_haps"]
+    H_all = np.diff(rh).astype(np.int64)
+    go, _ = phmm.genotype_offsets(H_all)
+    regs = sample_regions(batch, n_regions)
+    off, worst, ok = 0, 0.0, True
+    for k, g in enumerate(regs):
+        R, H = int(rr[g + 1] - rr[g]), int(H_all[g])
+        if k < n_check:
+            ref = oracle.genotype_region(ovals[off:off + R * H].reshape(R, H))
+            got = gl[int(go[g]):int(go[g]) + len(ref)]
+            err = np.abs(got - ref)
+            worst = max(worst, float((err / max(R, 1)).max()))
+            ok &= bool(np.all(err <= 1e-4 * R + 1e-12 * np.abs(ref)))
+        off += R * H
+    return dict(regions=min(n_check, len(regs)), max_err_per_read=worst, ok=ok)
 
 
 def run_oracle(batch, idx, cores):
@@ -659,13 +688,14 @@ def genotype_leg(phmm, torch, ctx, batch, out, stream, reps):
         if r > 0:
             times.append(e0.elapsed_time(e1))
     ms = min(times)
+    gl_h = gl.cpu().numpy()
     G = H * (H + 1) // 2
     terms = int((G * R).sum())
     het = int(((G - H) * R).sum())
     nbytes = 8 * int((R * H).sum()) + 8 * n_gl + 4 * len(H) + 24 * len(H)
     log("genotype likelihoods: %d regions, %.3g read terms (%.3g heterozygous) in %.3f ms"
         % (len(H), terms, het, ms))
-    return dict(ms=round(ms, 3), regions=len(H), genotypes=n_gl, read_terms=terms,
+    return gl_h, dict(ms=round(ms, 3), regions=len(H), genotypes=n_gl, read_terms=terms,
                 het_read_terms=het, g_terms_per_s=round(terms / (ms * 1e-3) / 1e9, 2),
                 gb_per_s=round(nbytes / (ms * 1e-3) / 1e9, 1),
                 note="diploid genotype log10-likelihoods of every region from the step's "
@@ -875,8 +905,13 @@ def main():
 
     genotype = None
     if args.genotype_reps > 0:
-        genotype = genotype_leg(phmm, torch, ctx, batch, out, stream, args.genotype_reps)
+        gl_h, genotype = genotype_leg(phmm, torch, ctx, batch, out, stream, args.genotype_reps)
         genotype["share_of_step"] = round(genotype["ms"] / ms_per_step, 5)
+        if cpu is not None:
+            genotype["parity_sample"] = genotype_parity(batch, args.cpu_regions, ovals, gl_h)
+            log("genotype parity on %d sampled regions: ok=%s"
+                % (genotype["parity_sample"]["regions"], genotype["parity_sample"]["ok"]))
+        del gl_h
 
     end_to_end = None
     if args.end_to_end:
