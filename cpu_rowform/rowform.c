@@ -35,7 +35,8 @@
 
 static double g_pow10[256];
 
-static void init_table(void)
+/* filled when the library is loaded, before any call can read it */
+__attribute__((constructor)) static void init_table(void)
 {
     for (int q = 0; q < 256; ++q) g_pow10[q] = pow(10.0, -q / 10.0);
 }
@@ -157,11 +158,6 @@ int rf_forward_pairs(const uint8_t* reads, const uint8_t* bq, const uint8_t* iq,
                      const uint8_t* haps, const uint64_t* hap_off, const uint32_t* pairs,
                      uint64_t n_pairs, int threads, double* out_log10, uint8_t* out_flags)
 {
-    static int inited = 0;
-    if (!inited) {
-        init_table();
-        inited = 1;
-    }
     int fail = 0;
 #pragma omp parallel num_threads(threads > 0 ? threads : omp_get_max_threads())
     {
