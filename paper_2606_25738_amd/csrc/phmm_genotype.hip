@@ -27,13 +27,13 @@
 //
 // Work mapping: one wavefront per region (grid-stride over regions).  The
 // powers p of a chunk of whole reads and their maxima m are staged in LDS
-// (underflowing terms read L itself, from the cache).  A region with G >= 64
-// genotypes gives lane t the genotypes t, t + 64, ...; one with fewer splits
-// the wavefront into 64 / gw groups of gw >= G lanes (gw a power of two),
-// group k taking the reads k, k + 64/gw, ... of every genotype, and adds the
-// groups' log-likelihoods at the end.  The arithmetic is FP64 (the powers,
-// then a multiply, frexp and two adds per read and genotype), so the kernel
-// is bound by VALU issue.
+// (underflowing terms read L itself, from the cache).  Genotypes are taken 64
+// per pass; a pass of rem < 64 genotypes (a small region, or the last pass of
+// a larger one) splits the wavefront into 64 / gw groups of gw >= rem lanes
+// (gw a power of two), group k taking the reads k, k + 64/gw, ... of every
+// genotype, and adds the groups' log-likelihoods at the end.  The arithmetic
+// is FP64 (the powers, then a multiply, frexp and two adds per read and
+// genotype), so the kernel is bound by VALU issue.
 #include <math.h>
 #include <stdint.h>
 
@@ -83,22 +83,21 @@ __global__ __launch_bounds__(kGtLane) void genotype_kernel(
             if (lane == 0) best[reg] = 0xFFFFFFFFu;
             continue;
         }
-        uint32_t gw = kGtLane;  // lanes per read group
-        if (G < kGtLane) {
-            gw = 1;
-            while (gw < G) gw <<= 1;
-        }
-        const uint32_t groups = kGtLane / gw;
-        const uint32_t sub = lane & (gw - 1);
-        const uint32_t grp = lane / gw;
         // >= 1 since H <= PHMM_GT_MAX_HAPS <= kGtLds
         const uint32_t rchunk = min(kGtLds / H, kGtReads);
         uint32_t staged_r0 = 0xFFFFFFFFu;     // first read of the chunk in LDS
         double bv = -INFINITY;
         uint32_t bi = 0xFFFFFFFFu;
-        for (uint64_t g0 = 0; g0 < G; g0 += gw) {
+        for (uint64_t g0 = 0; g0 < G; g0 += kGtLane) {
+            // genotypes g0 .. g0 + rem - 1 in this pass, on groups of gw lanes
+            const uint32_t rem = (uint32_t)min(G - g0, (uint64_t)kGtLane);
+            uint32_t gw = 1;
+            while (gw < rem) gw <<= 1;
+            const uint32_t groups = kGtLane / gw;
+            const uint32_t sub = lane & (gw - 1);
+            const uint32_t grp = lane / gw;
             const uint64_t gi = g0 + sub;
-            const bool act = gi < G;
+            const bool act = sub < rem;
             uint32_t a = 0, b = 0;
             if (act) genotype_pair((uint32_t)gi, a, b);
             double add = 0.0;   // sum of m, and of the underflowing reads' terms
