@@ -16,7 +16,9 @@
  * evaluated in the row-level formulation of Section 3.1 (eq.5-7): a whole
  * DP row is updated at once and the within-row Delete chain is resolved as
  * a first-order linear recurrence by a wavefront scan (Section 3.4,
- * Algorithm 1).
+ * Algorithm 1).  It also turns a region's read x haplotype likelihoods into
+ * diploid genotype likelihoods (phmm_genotype_batch), the step that follows
+ * the PairHMM in the pipeline of Section 1.
  *
  * Value conventions
  *   - bases are upper-case ASCII 'A','C','G','T' or 'N'; 'N' in either
