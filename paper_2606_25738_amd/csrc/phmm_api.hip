@@ -336,7 +336,8 @@ static bool class_used(const Policy& pol, int cls)
     return pol.force_class < 0 || cls == pol.force_class || cls == kNumClasses - 1;
 }
 
-static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s, uint32_t max_hap_len)
+static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s, uint32_t max_hap_len,
+                   uint32_t max_read_len)
 {
     const Policy pol = batch_policy(c, b.n_pairs, max_hap_len);
     Tables t;
@@ -359,21 +360,42 @@ static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s, uint32_
         // 0 or an insertion byte above 65), get one wavefront per SIMD.
         const int n_cap = (int)std::min<uint64_t>(b.n_pairs, 1u << 30);
         auto cap = [&](int grid) { return std::min(grid, n_cap); };
+        // In a small batch every short pair fits the forced class, so the
+        // widest class, the general FP32 kernels, the widest FP64 class and,
+        // when no pair can be long, the long kernels only catch exceptions:
+        // they get one wavefront per CU (the forced FP64 class, which runs
+        // the rejected pairs in FP32 mode, one per SIMD).  Every kernel is a
+        // persistent loop over its queue, so any grid completes the same work.
+        const bool small = b.n_pairs <= kSmallBatchPairs && c->opt.force_class < 0;
+        auto net = [&](int grid, int per_cu) {
+            return small ? std::min(grid, per_cu * c->cus) : grid;
+        };
         if (pol.precision == PHMM_FP32_RERUN) {
             for (int cls = 0; cls < kNumClasses; ++cls)
                 if (class_used(pol, cls))
-                    launch_short(kFast32, cls, cap(c->grid_short[kFast32][cls]), s, b, t, w, pol);
+                    launch_short(kFast32, cls,
+                                 cls == pol.force_class ? cap(c->grid_short[kFast32][cls])
+                                                        : net(cap(c->grid_short[kFast32][cls]), 1),
+                                 s, b, t, w, pol);
             for (int cls = 0; cls < kNumClasses; ++cls)
                 if (class_used(pol, cls))
-                    launch_short(kGen32, cls, cap(std::min(c->grid_short[kGen32][cls], 4 * c->cus)),
+                    launch_short(kGen32, cls,
+                                 net(cap(std::min(c->grid_short[kGen32][cls], 4 * c->cus)), 1),
                                  s, b, t, w, pol);
         }
         if (timed) HIP_TRY(hipEventRecord(c->ev[2], s));
         for (int cls = 0; cls < kNumClasses; ++cls)
             if (class_used(pol, cls))
-                launch_short(kAll64, cls, cap(c->grid_short[kAll64][cls]), s, b, t, w, pol);
+                launch_short(kAll64, cls,
+                             cls != pol.force_class ? net(cap(c->grid_short[kAll64][cls]), 1)
+                             : pol.precision == PHMM_FP64_PLAIN ? cap(c->grid_short[kAll64][cls])
+                                                                : net(cap(c->grid_short[kAll64][cls]), 4),
+                             s, b, t, w, pol);
         if (timed) HIP_TRY(hipEventRecord(c->ev[3], s));
-        launch_long(s, c->grid_long, b, t, w, pol);
+        const bool no_long = max_hap_len <= kShortMaxCols && max_read_len <= pol.fp32_max_rows;
+        const int lgrid[2] = {small && no_long ? std::min(c->grid_long[0], c->cus) : c->grid_long[0],
+                              small && no_long ? std::min(c->grid_long[1], c->cus) : c->grid_long[1]};
+        launch_long(s, lgrid, b, t, w, pol);
     } else if (timed) {
         HIP_TRY(hipEventRecord(c->ev[2], s));
         HIP_TRY(hipEventRecord(c->ev[3], s));
@@ -491,7 +513,8 @@ extern "C" int phmm_forward_batch_async(phmm_ctx* c, const phmm_device_batch* db
     const int rc = device_batch(c, db, d_out, d_flags, d_ws, ws_bytes, &b);
     if (rc != PHMM_OK) return rc;
     HIP_TRY(hipSetDevice(c->device));
-    return enqueue(c, b, d_ws, static_cast<hipStream_t>(hip_stream), db->max_hap_len);
+    return enqueue(c, b, d_ws, static_cast<hipStream_t>(hip_stream), db->max_hap_len,
+                   db->max_read_len);
 }
 
 int phmm::forward_device_batch_sync(phmm_ctx* c, const phmm_device_batch* db, double* d_out,
@@ -838,7 +861,7 @@ extern "C" int phmm_forward_batch(phmm_ctx* c, const uint8_t* reads, const uint8
             bk.n_pairs = p0[k + 1] - p0[k];
             bk.out = b.out + p0[k];
             bk.flags = b.flags + p0[k];
-            rc = enqueue(c, bk, A + o_ws, s, max_k);
+            rc = enqueue(c, bk, A + o_ws, s, max_k, UINT32_MAX);
             if (rc != PHMM_OK) return rc;
             HIP_TRY(hipMemcpyAsync(c->h_chunk + k, A + o_ws, sizeof(Counters), hipMemcpyDeviceToHost, s));
         }
