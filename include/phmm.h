@@ -229,7 +229,10 @@ size_t phmm_workspace_bytes(phmm_ctx* ctx, uint64_t n_pairs, uint32_t max_read_l
  * phmm_workspace_bytes(...) bytes of device memory.  Only the host-visible
  * fields of *b are checked (null pointers, bounds, workspace size); device
  * contents are trusted.  A batch of at most 8192 pairs is packed in one
- * narrow class chosen from max_hap_len, as in phmm_forward_batch.  Errors
+ * narrow class chosen from max_hap_len, as in phmm_forward_batch; the
+ * launches that only catch exceptions (pairs that do not fit that class,
+ * FP32 rejects, and long pairs when max_hap_len <= 64 x 24 and max_read_len
+ * <= fp32_max_rows) then get small grids.  Errors
  * detected on the device (watchdog) are reported by phmm_device_status()
  * after the stream has passed the call.
  */
