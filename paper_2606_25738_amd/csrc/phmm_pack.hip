@@ -351,36 +351,35 @@ __global__ __launch_bounds__(256) void pack_chunk_sum_kernel(Work w)
 }
 
 // Pass 2b (one workgroup): chunk offsets per segment, segment bases of the
-// pack array and the capacity of the rerun item lists.
+// pack array and the capacity of the rerun item lists.  Each wavefront scans
+// whole segments (lane t sums a run of consecutive chunks, a shuffle scan
+// adds the lanes up), so no barrier is needed until the segment totals.
 __global__ __launch_bounds__(1024) void pack_scan_kernel(Work w)
 {
-    __shared__ uint32_t part[1024];
     __shared__ uint32_t seg_total[kSeg];
     const int t = (int)threadIdx.x;
+    const int lane = t & (kWave - 1);
     const uint32_t n = w.n_scan_chunks;
-    const uint32_t per = (n + 1023u) / 1024u;
-    const uint32_t lo = (uint32_t)t * per, hi = lo + per < n ? lo + per : n;
-    for (int s = 0; s < kSeg; ++s) {
+    const uint32_t per = (n + kWave - 1u) / kWave;
+    const uint32_t lo = (uint32_t)lane * per, hi = lo + per < n ? lo + per : n;
+    for (int s = t / kWave; s < kSeg; s += (int)blockDim.x / kWave) {
         uint32_t* cp = w.chunk_part + (size_t)s * n;
         uint32_t sum = 0;
         for (uint32_t q = lo; q < hi; ++q) sum += cp[q];
-        part[t] = sum;
-        __syncthreads();
-        for (int d = 1; d < 1024; d <<= 1) {
-            const uint32_t y = t >= d ? part[t - d] : 0u;
-            __syncthreads();
-            part[t] += y;
-            __syncthreads();
+        uint32_t inc = sum;  // inclusive scan of the lane sums
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t y = __shfl_up(inc, d, kWave);
+            if (lane >= d) inc += y;
         }
-        uint32_t acc = part[t] - sum;
+        uint32_t acc = inc - sum;
         for (uint32_t q = lo; q < hi; ++q) {
             const uint32_t v = cp[q];
             cp[q] = acc;  // becomes the chunk's offset in the segment
             acc += v;
         }
-        if (t == 1023) seg_total[s] = part[1023];
-        __syncthreads();
+        if (lane == kWave - 1) seg_total[s] = inc;
     }
+    __syncthreads();
     if (t == 0) {
         Counters* c = w.ctr;
         uint32_t acc = 0;
