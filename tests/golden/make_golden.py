@@ -27,6 +27,11 @@ CASES = [
     ("TTAC", "GTTACA", [10, 20, 30, 40], [40, 40, 40, 40], [40, 40, 40, 40], [10] * 4),
     ("NACG", "ACGN", [20, 20, 20, 20], [30] * 4, [30] * 4, [10] * 4),
     ("CCCCCC", "CCCC", [40] * 6, [10] * 6, [10] * 6, [10] * 6),
+    # insertion and/or deletion Phred 0: T_MI or T_MD = 1, so 1 - T_MI - T_MD
+    # is negative and T_MM is clamped to 0 on those rows
+    ("ACGT", "ACGTA", [20, 30, 20, 10], [0, 40, 40, 30], [40, 0, 40, 30], [10, 10, 10, 20]),
+    ("GGA", "GAGA", [30, 30, 30], [0, 0, 10], [0, 20, 0], [10, 10, 10]),
+    ("TAC", "TAC", [40, 10, 40], [10, 0, 10], [0, 10, 10], [10, 20, 10]),
 ]
 
 
@@ -39,7 +44,8 @@ def priors(bq, iq, dq, gq):
     for b, i, d, g in zip(bq, iq, dq, gq):
         assert b % 10 == 0 and i % 10 == 0 and d % 10 == 0 and g % 10 == 0
         eps, tmi, tmd, gg = prob(b), prob(i), prob(d), prob(g)
-        rows.append([1 - eps, eps / 3, 1 - (tmi + tmd), 1 - gg, 1 - gg, tmi, gg, tmd, gg])
+        tmm = max(Fraction(0), 1 - (tmi + tmd))  # clamped at 0 (T_MI + T_MD may exceed 1)
+        rows.append([1 - eps, eps / 3, tmm, 1 - gg, 1 - gg, tmi, gg, tmd, gg])
     return rows
 
 

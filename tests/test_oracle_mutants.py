@@ -20,6 +20,7 @@ sys.path.insert(0, ROOT)
 from oracle import exact  # noqa: E402
 
 SRC = os.path.join(ROOT, "oracle", "phmm_oracle.c")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "exact_small.txt")
 
 MUTANTS = {
     "tIM_replaced_by_tDM": ("double b = pr[P_TIM] * Ip[j - 1];",
@@ -33,6 +34,9 @@ MUTANTS = {
     "divisor_k_plus_1": ("return ldexp(1.0, 1020) / (double)k;",
                          "return ldexp(1.0, 1020) / (double)(k + 1);"),
     "mismatch_prior_033": ("r[P_PX] = eps / 3.0;", "r[P_PX] = eps * 0.33;"),
+    "mismatch_prior_eps": ("r[P_PX] = eps / 3.0;", "r[P_PX] = eps;"),
+    "missing_clamp": ("if (tmm < 0.0) tmm = 0.0;", ""),
+    "clamp_at_one_minus_ins": ("if (tmm < 0.0) tmm = 0.0;", "if (tmm < 0.0) tmm = 1.0 - tmi;"),
     "final_sum_without_I": ("for (int j = 1; j <= k; ++j) s = s + (Mp[j] + Ip[j]);\n    *S = s;\n    *E = ex;",
                             "for (int j = 1; j <= k; ++j) s = s + Mp[j];\n    *S = s;\n    *E = ex;"),
     "D00_zero": ("Mc[0] = 0.0; Ic[0] = 0.0; Dc[0] = 0.0;\n        for (int j = 1; j <= k; ++j) {\n            double p = emission(pr, r, hap[j - 1]);\n            double a",
@@ -99,7 +103,22 @@ def run_pins(lib):
     lib.oracle_forward_one(rp, *[a[1] for a in args], 1, hp, 3, 0, ctypes.byref(out),
                            ctypes.byref(S), ctypes.byref(E))
     want = math.log10(0.9 / 3 * (2 * (1 - 0.01) + 0.01 / 3))
-    return abs(out.value - want) < 1e-12
+    if abs(out.value - want) >= 1e-12:
+        return False
+    # exact rational likelihoods from Phred bytes (tests/golden/exact_small.txt),
+    # including rows whose T_MI + T_MD exceeds 1 (clamped T_MM)
+    for line in open(GOLDEN):
+        if line.startswith("#") or not line.strip():
+            continue
+        read, hap, bq, iq, dq, gq, lg, _ = line.split()
+        ra, rp = _u8(read.encode())
+        ha, hp = _u8(hap.encode())
+        q = [_u8(bytes(int(x) for x in v.split(","))) for v in (bq, iq, dq, gq)]
+        lib.oracle_forward_one(rp, *[a[1] for a in q], len(read), hp, len(hap), 0,
+                               ctypes.byref(out), ctypes.byref(S), ctypes.byref(E))
+        if not abs(out.value - float(lg)) < 1e-12:
+            return False
+    return True
 
 
 def test_unmutated_copy_passes(tmp_path):
