@@ -19,6 +19,7 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import paper_2606_25738_amd as phmm  # noqa: E402
 import synth  # noqa: E402
+from edge_batch import edge_pairs, make_batch, rnd  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -172,50 +173,11 @@ def test_deterministic(ctx32):
     assert np.array_equal(a.view(np.uint64), c.view(np.uint64)) and np.array_equal(fa, fc)
 
 
-def make_batch(pairs):
-    """pairs: list of (read, hap, bq, iq, dq, gq) with bytes / int arrays."""
-    reads, haps, bq, iq, dq, gq, ro, ho, pl = [], [], [], [], [], [], [0], [0], []
-    for r, h, q, i, d, g in pairs:
-        reads.append(np.frombuffer(r, np.uint8))
-        haps.append(np.frombuffer(h, np.uint8))
-        for lst, v in ((bq, q), (iq, i), (dq, d), (gq, g)):
-            lst.append(np.broadcast_to(np.asarray(v, np.uint8), (len(r),)))
-        ro.append(ro[-1] + len(r))
-        ho.append(ho[-1] + len(h))
-        pl.append((len(ro) - 2, len(ho) - 2))
-    cat = lambda x: np.ascontiguousarray(np.concatenate(x).astype(np.uint8))
-    return dict(reads=cat(reads), base_quals=cat(bq), ins_quals=cat(iq), del_quals=cat(dq),
-                gcp=cat(gq), read_offsets=np.array(ro, np.uint64),
-                haplotypes=cat(haps), hap_offsets=np.array(ho, np.uint64),
-                pair_list=np.array(pl, np.uint32))
-
-
-def rnd(rng, n, alpha=b"ACGT"):
-    a = np.frombuffer(alpha, np.uint8)
-    return bytes(a[rng.integers(0, len(a), n)])
-
-
 @pytest.mark.skip(reason="hung once on the GPU after the FP32 kernel was split into fast and "
                          "general kernels (the rest of the suite passed); the cause is not found "
                          "yet, so the case stays off the GPU until it is")
 def test_edge_cases(ctx32, ctx64):
-    rng = np.random.default_rng(5)
-    src = rnd(rng, 3000)
-    pairs = [
-        (b"A", b"A", 30, 45, 45, 10),
-        (b"A", b"C", 30, 45, 45, 10),
-        (b"ACGT", b"A", 20, 45, 45, 10),
-        (b"A", rnd(rng, 97), 20, 45, 45, 10),
-        (b"N" * 30, rnd(rng, 50), 20, 45, 45, 10),
-        (rnd(rng, 30), b"N" * 40, 20, 45, 45, 10),
-        (rnd(rng, 40, b"ACGTN"), rnd(rng, 60, b"ACGTN"), 25, 40, 40, 10),
-        (src[100:250], src[90:90 + 64 * 4], 30, 45, 45, 10),           # exactly 64 lanes x 4
-        (src[100:250], src[90:90 + 64 * 24], 30, 45, 45, 10),          # widest short pair
-        (src[100:250], src[90:90 + 64 * 24 + 1], 30, 45, 45, 10),      # first long pair
-        (src[0:150], src[0:150], 0, 0, 0, 0),                           # Phred 0 everywhere
-        (src[0:150], src[0:150], 255, 255, 255, 255),                   # Phred 255 everywhere
-        (src[5:120], src[0:300], np.arange(115) % 60, 30, 30, np.arange(115) % 40 + 1),
-    ]
+    pairs = edge_pairs()
     b = make_batch(pairs)
     for c, plain in ((ctx64, True), (ctx32, False)):
         out, fl = phmm.phmm_forward_batch(c, b)
