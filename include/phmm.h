@@ -88,8 +88,17 @@ extern "C" {
 
 typedef struct phmm_options {
     int precision;          /* PHMM_FP32_RERUN (default) or PHMM_FP64_PLAIN          */
-    double accept_min_sum;  /* FP32 acceptance threshold on the scaled sum S32 =
-                               L * 2^120; default 1e-28 (log10 L >= -64.12)           */
+    double accept_min_sum;  /* FP32 acceptance threshold, in [1e-30, 3e38]; default
+                               1e-28.  An FP32 result is accepted iff its scaled sum
+                               is finite, > 0 and >= accept_min_sum.  Reads of up to
+                               256 rows keep the fixed scale, S32 = L * 2^120 (1e-28:
+                               log10 L >= -64.12).  Longer reads are rescaled by an
+                               exact power of two 2^f at 64-row windows (f >= 33 each
+                               time), so S32 = L * 2^(120 + sum f) there and such
+                               reads are accepted further down; a pair of such a pack
+                               whose own values had fallen under 2^-100 at a rescale
+                               is rerun whatever its sum.  A threshold above 2^120
+                               reruns every pair in FP64.                             */
     int force_class;        /* -1: the packer picks columns-per-lane per region;
                                >= 0: force this class index (see phmm_class_n)       */
     int one_pair_per_wave;  /* 1: no packing, every pair gets its own wavefront      */
@@ -138,7 +147,9 @@ int phmm_num_classes(void);
 int phmm_class_n(int c);
 
 /*
- * Batched forward pass (host buffers, synchronous).
+ * Batched forward pass (host buffers, synchronous): log10 of the likelihood
+ * L of eq.4 for every pair, from the recurrences of eq.1-3 (Section 2),
+ * computed in the row-level formulation of Section 3.1 (eq.5-7).
  *
  * reads, base_quals, ins_quals, del_quals, gcp : n_bases bytes each, the
  *     reads one after another; read r is bytes [read_offsets[r],
@@ -187,8 +198,14 @@ int phmm_validate_batch(const uint8_t* reads, const uint8_t* base_quals,
                         uint32_t* max_read_len, uint32_t* max_hap_len);
 
 /*
- * One pair, FP64 (PHMM_FP64_PLAIN on a library-owned default context on
- * device 0).  Arrays hold read_len resp. hap_len bytes.
+ * One pair, FP64: log10 L of eq.4 (Section 2, eq.1-4; row-level evaluation
+ * of Section 3.1) for one read and one haplotype, the plain drop-in for a
+ * per-pair caller.  Runs PHMM_FP64_PLAIN on a library-owned default context
+ * on device 0 (created on the first call, guarded by a mutex, kept until the
+ * process ends).  Arrays hold read_len resp. hap_len bytes (read_len >= 1,
+ * hap_len >= 1); the bases and limits are validated as in
+ * phmm_forward_batch.  Errors: PHMM_EINVAL (NULL argument, empty sequence,
+ * bad base), PHMM_ERANGE, PHMM_EDEVICE.
  */
 int phmm_forward_one(const uint8_t* read, const uint8_t* base_quals,
                      const uint8_t* ins_quals, const uint8_t* del_quals,
@@ -221,8 +238,11 @@ size_t phmm_workspace_bytes(phmm_ctx* ctx, uint64_t n_pairs, uint32_t max_read_l
                             uint32_t max_hap_len);
 
 /*
- * Stream-ordered forward pass over device-resident inputs: packing, FP32
- * kernels, FP64 reruns and long pairs are all enqueued on hip_stream (a
+ * Stream-ordered forward pass over device-resident inputs: the same
+ * likelihoods as phmm_forward_batch (eq.1-4 of Section 2, row-level
+ * formulation of Section 3.1, Delete row by the scan of Section 3.4).
+ * Packing, FP32 kernels, FP64 reruns and long pairs are all enqueued on
+ * hip_stream (a
  * hipStream_t; NULL = the null stream) with no host synchronisation and no
  * allocation.  d_out_log10 (n_pairs doubles) and d_flags (n_pairs bytes, or
  * NULL) are device pointers; d_workspace holds at least

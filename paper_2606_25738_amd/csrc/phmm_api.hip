@@ -130,12 +130,21 @@ static Policy make_policy(const phmm_options& o, const float (&cost)[2][kNumClas
     return p;
 }
 
+// Smallest accepted FP32 threshold: ten decades below the default 1e-28 is
+// not allowed, two are (see check_options).
+constexpr double kAcceptFloor = 1e-30;
+
 static int check_options(const phmm_options& o)
 {
     if (o.precision != PHMM_FP32_RERUN && o.precision != PHMM_FP64_PLAIN)
         return fail(PHMM_EINVAL, "options.precision must be PHMM_FP32_RERUN or PHMM_FP64_PLAIN");
-    if (!(o.accept_min_sum > 0.0) || o.accept_min_sum > 1e30)
-        return fail(PHMM_EINVAL, "options.accept_min_sum must be in (0, 1e30]");
+    // The FP32 kernels compare the scaled sum with the threshold held as a
+    // float.  Below kAcceptFloor an accepted sum could sit so close to
+    // FP32's smallest normal numbers that the pair's dominant cells lose
+    // precision; above 3e38 the float would overflow.  Any threshold above
+    // every possible scaled sum (2^120) reruns every pair in FP64.
+    if (!(o.accept_min_sum >= kAcceptFloor) || !(o.accept_min_sum <= 3.0e38))
+        return fail(PHMM_EINVAL, "options.accept_min_sum must be in [%g, 3e38]", kAcceptFloor);
     if (o.force_class < -1 || o.force_class >= kNumClasses)
         return fail(PHMM_EINVAL, "options.force_class must be -1 or 0..%d", kNumClasses - 1);
     if (o.route_diverse_fp64 != 0 && o.route_diverse_fp64 != 1)

@@ -362,8 +362,10 @@ void short_kernel(Batch b, Tables t, Work w, Policy pol)
             off = pinfo[2][lane];
             const double S = (double)s;
             if (kFP32) {
-                reject = ((sdamage >> lane) & 1u) != 0u || !(S >= (double)pol.accept_min_sum) ||
-                         !(S < 3.0e38);
+                // a sum of 0 is rejected whatever the threshold: L > 0 may
+                // have underflowed in FP32
+                reject = ((sdamage >> lane) & 1u) != 0u || !(S > 0.0) ||
+                         !(S >= (double)pol.accept_min_sum) || !(S < 3.0e38);
                 if (!reject) {
                     b.out[pair] = log10_scaled_f32((float)s, ScaleOf<R>::exp + fexp);
                     if (b.flags) b.flags[pair] = 0x01;  // FP32 accepted

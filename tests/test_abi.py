@@ -193,3 +193,24 @@ def test_server_rejects_bad_options():
         with pytest.raises(phmm.PhmmError) as e:
             phmm.Server(**kw)
         assert e.value.code == phmm.PHMM_EINVAL, kw
+
+
+@pytest.mark.parametrize("value", [0.0, 1e-45, 1e-38, 9.9e-31, float("nan"), 1e39])
+def test_accept_threshold_outside_range_rejected(value):
+    """The FP32 acceptance threshold is held as a float in the kernels: values
+    under the 1e-30 floor (near FP32's smallest normals, or 0 after rounding)
+    and values a float cannot hold are refused before any device work."""
+    with pytest.raises(phmm.PhmmError) as e:
+        phmm.Context(accept_min_sum=value)
+    assert e.value.code == phmm.PHMM_EINVAL and "accept_min_sum" in str(e.value)
+
+
+def test_forward_one_argument_errors():
+    """phmm_forward_one checks its arguments before touching a device."""
+    q = np.full(4, 30, np.uint8)
+    with pytest.raises(phmm.PhmmError) as e:
+        phmm.phmm_forward_one(b"", q[:0], q[:0], q[:0], q[:0], b"ACGT")
+    assert e.value.code == phmm.PHMM_EINVAL and "empty" in str(e.value)
+    with pytest.raises(phmm.PhmmError) as e:
+        phmm.phmm_forward_one(b"ACGT", q, q, q, q, b"")
+    assert e.value.code == phmm.PHMM_EINVAL

@@ -86,13 +86,65 @@ def test_one_region_fp32_rerun_policy():
         out, fl = phmm.phmm_forward_batch(c, b)
     want, d = check(b, out, fl)
     rerun = (fl & phmm.PHMM_FLAG_RERUN) != 0
-    # pairs above the acceptance threshold are never rerun; below it a pair
-    # is accepted only if its pack was rescaled and its sum then cleared the
-    # threshold (the error bound is checked above either way)
+    # reads of 100 rows keep the fixed scale 2^120 (window rescaling starts
+    # above 256 rows), so the acceptance rule is exact: a pair is rerun if and
+    # only if its scaled sum L * 2^120 is under 1e-28, i.e. log10 L under
+    # -64.1236, outside a band of +-1e-3 for FP32 rounding
+    assert int(np.diff(b["read_offsets"].astype(np.int64)).max()) <= 256
     assert not np.any(rerun[want > THRESH + 1e-3])
-    assert np.all(rerun[want < THRESH - 200])
+    assert np.all(rerun[want < THRESH - 1e-3])
+    assert (want < THRESH - 1e-3).sum() > 100
     say("one_region fp32: rerun %d of %d, max err fp32 %.3g" % (rerun.sum(), len(out),
                                                           d[~rerun].max() if (~rerun).any() else 0))
+
+
+def test_threshold_forced_high_reruns_everything():
+    """With the acceptance threshold above every possible scaled sum (L <= 1,
+    so S32 = L * 2^120 < 2e38) every FP32 result is rejected, and the reruns
+    equal the plain FP64 path to rounding."""
+    b = synth.generate("batched_uneven", 5, 4)
+    with phmm.Context(accept_min_sum=2e38) as c:
+        out, fl = phmm.phmm_forward_batch(c, b)
+    with phmm.Context(precision=phmm.PHMM_FP64_PLAIN) as c:
+        ref, fr = phmm.phmm_forward_batch(c, b)
+    assert np.all(fl == (phmm.PHMM_FLAG_RERUN | phmm.PHMM_FLAG_FP64))
+    assert np.all(fr == phmm.PHMM_FLAG_FP64)
+    assert np.abs(out - ref).max() <= 1e-12
+    n = len(b["pair_list"])
+    check(b, out, fl, np.arange(0, n, max(1, n // 300)))
+
+
+def test_threshold_at_floor_accepts_more_and_stays_in_bound():
+    """At the smallest threshold the library accepts (1e-30, two decades
+    under the default) exactly the pairs with log10 L >= -30 - 120 log10 2
+    are accepted in FP32 (reads of 100 rows: fixed scale), no finite pair
+    comes back -inf, and every result stays within its bound."""
+    b = near_threshold_batch()
+    t30 = -30.0 - 120 * math.log10(2.0)
+    for thr, tlog in ((1e-30, t30), (1e-28, THRESH)):
+        with phmm.Context(accept_min_sum=thr) as c:
+            out, fl = phmm.phmm_forward_batch(c, b)
+        want, d = check(b, out, fl)
+        rerun = (fl & phmm.PHMM_FLAG_RERUN) != 0
+        assert not np.any(rerun[want > tlog + 1e-3]) and np.all(rerun[want < tlog - 1e-3])
+        assert np.all(np.isfinite(out))
+    assert ((want > t30 + 1e-3) & (want < THRESH - 1e-3)).sum() >= 5  # the band 1e-30..1e-28
+
+
+def near_threshold_batch():
+    """96 reads of 100 bp from one 200 bp haplotype with 12-23 substitutions
+    each (base quality 25-35): log10 L from about -83 to -44, six pairs
+    between the scaled sums 1e-30 and 1e-28, none within 0.08 of either."""
+    rng = np.random.default_rng(21)
+    hap = rnd(rng, 200)
+    pairs = []
+    for _ in range(96):
+        m, off = int(rng.integers(12, 24)), int(rng.integers(0, 100))
+        rd = bytearray(hap[off:off + 100])
+        for p in rng.choice(100, m, replace=False):
+            rd[p] = ord("ACGT"[("ACGT".index(chr(rd[p])) + int(rng.integers(1, 4))) % 4])
+        pairs.append((bytes(rd), hap, rng.integers(25, 36, 100), 45, 45, 10))
+    return make_batch(pairs)
 
 
 def test_unrelated_haplotypes_start_in_fp64(ctx32):
@@ -539,3 +591,30 @@ def test_autotune_costs_and_results():
         assert np.array_equal(c.class_costs(), default)
         with pytest.raises(phmm.PhmmError):
             c.set_class_costs(-default)
+
+
+def test_forward_one_drop_in():
+    """phmm_forward_one, the per-pair drop-in (FP64 plain on the library's
+    default context), through the C ABI: short pairs of the one-region
+    workload, one long pair (three tiles of the long kernel) and per-row
+    quality arrays, each against the oracle within the FP64 bound."""
+    b = synth.generate("one_region")
+    ro, ho = b["read_offsets"].astype(np.int64), b["hap_offsets"].astype(np.int64)
+    rng = np.random.default_rng(31)
+    cases = []
+    for q in rng.choice(len(b["pair_list"]), 6, replace=False):
+        r, h = (int(x) for x in b["pair_list"][q])
+        sl = slice(ro[r], ro[r + 1])
+        cases.append((b["reads"][sl], b["base_quals"][sl], b["ins_quals"][sl], b["del_quals"][sl],
+                      b["gcp"][sl], b["haplotypes"][ho[h]:ho[h + 1]]))
+    hap = np.frombuffer(rnd(rng, 2500), np.uint8)
+    read = hap[700:1000].copy()
+    read[rng.choice(300, 6, replace=False)] = np.frombuffer(b"ACGTAC", np.uint8)
+    cases.append((read, rng.integers(10, 41, 300).astype(np.uint8), np.full(300, 40, np.uint8),
+                  np.full(300, 40, np.uint8), rng.integers(5, 30, 300).astype(np.uint8), hap))
+    for rd, bq, iq, dq, gq, hp in cases:
+        got = phmm.phmm_forward_one(rd, bq, iq, dq, gq, hp)
+        one = make_batch([(bytes(rd), bytes(hp), bq, iq, dq, gq)])
+        want = oracle.forward_pairs(one, rescale=True)[0]
+        say("forward_one l=%d k=%d: %.10f vs oracle %.10f" % (len(rd), len(hp), got, want))
+        assert abs(got - want) <= TOL64
