@@ -260,6 +260,30 @@ int phmm_forward_batch_async(phmm_ctx* ctx, const phmm_device_batch* b, double* 
                              uint8_t* d_flags, void* d_workspace, size_t ws_bytes,
                              void* hip_stream);
 
+/*
+ * phmm_forward_batch_async without a workspace argument, for callers that
+ * cannot allocate device memory: code being captured into a HIP graph, tight
+ * serving loops, harnesses that forbid hipMalloc.  The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine); its scratch
+ * memory (counters, packs, rerun queues, long lists and the long kernels'
+ * ring buffers) is a library-owned static device array of
+ * PHMM_NOALLOC_SCRATCH_MIB MiB that each GPU holds from library load until
+ * the process ends, looked up once per device by phmm_create.  A batch may
+ * hold at most PHMM_NOALLOC_MAX_PAIRS pairs (PHMM_ERANGE beyond); the long
+ * kernels run at most 1024 wavefronts each.  Results equal those of
+ * phmm_forward_batch_async on the same batch.  The counters the kernels need
+ * at zero are cleared by the call's first kernel on the stream.  Every call
+ * on one GPU shares that GPU's array, which keeps the last call's contents:
+ * calls that overlap on one GPU (other streams, other contexts, other host
+ * threads) race and give wrong results; serialise them (one stream, or
+ * events).  phmm_device_status / phmm_last_counts do not apply (there is no
+ * caller workspace).  Errors: as phmm_forward_batch_async, plus PHMM_ERANGE.
+ */
+#define PHMM_NOALLOC_SCRATCH_MIB 64u
+#define PHMM_NOALLOC_MAX_PAIRS (1u << 19)
+int phmm_forward_batch_noalloc(phmm_ctx* ctx, const phmm_device_batch* b, double* d_out_log10,
+                               uint8_t* d_flags, void* hip_stream);
+
 /* Synchronises with the stream of the last async call and returns PHMM_OK or
  * the error the device recorded for it (PHMM_ETIMEOUT). */
 int phmm_device_status(phmm_ctx* ctx, void* d_workspace);

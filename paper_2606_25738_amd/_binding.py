@@ -134,6 +134,7 @@ def lib():
             L.phmm_workspace_bytes.restype = ctypes.c_size_t
             L.phmm_forward_batch_async.argtypes = [vp, ctypes.POINTER(_DeviceBatch), vp, vp, vp,
                                                    ctypes.c_size_t, vp]
+            L.phmm_forward_batch_noalloc.argtypes = [vp, ctypes.POINTER(_DeviceBatch), vp, vp, vp]
             L.phmm_device_status.argtypes = [vp, vp]
             L.phmm_last_counts.argtypes = [vp, vp, ctypes.POINTER(_Counts)]
             L.phmm_last_timing.argtypes = [vp, ctypes.POINTER(_Timing)]
@@ -377,6 +378,16 @@ def phmm_forward_batch_async(ctx: Context, db: DeviceBatch, out, flags, workspac
         ctx.handle, ctypes.byref(s), out.data_ptr(),
         flags.data_ptr() if flags is not None else None, workspace.data_ptr(),
         workspace.numel() * workspace.element_size(), h))
+
+
+def phmm_forward_batch_noalloc(ctx: Context, db: DeviceBatch, out, flags, stream=None):
+    """phmm_forward_batch_async with the library's static device scratch
+    instead of a caller workspace (allocates nothing)."""
+    s = db.struct()
+    h = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    _check(lib().phmm_forward_batch_noalloc(
+        ctx.handle, ctypes.byref(s), out.data_ptr(),
+        flags.data_ptr() if flags is not None else None, h))
 
 
 def genotype_offsets(region_haps) -> tuple[np.ndarray, int]:

@@ -198,6 +198,39 @@ extern "C" void phmm_destroy(phmm_ctx* c)
     delete c;
 }
 
+// ---------------------------------------------------------------- scratch
+// Device scratch of phmm_forward_batch_noalloc: the workspace of a batch of
+// up to PHMM_NOALLOC_MAX_PAIRS pairs with the long kernels' grids capped at
+// kNoAllocLongGrid wavefronts (their ring slots are most of it).  Every GPU
+// the library runs on holds its own copy until the process ends; the host
+// reaches a device's copy only through the address hipGetSymbolAddress
+// returns with that device current (the array's name is a host-side stand-in).
+constexpr size_t kScratchBytes = (size_t)PHMM_NOALLOC_SCRATCH_MIB << 20;
+// At least the tiles of the longest haplotype (2^20 / 1024 columns), so a
+// pair's tiles always fit the resident grid at once.
+constexpr int kNoAllocLongGrid = 1024;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static void* g_scratch[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// Address of `device`'s scratch array, looked up once per device with that
+// device current (the caller has made it current).
+static int scratch_for(int device, void** out)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return fail(PHMM_EDEVICE, "device %d beyond the %d the library tracks", device, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(PHMM_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch[device] = p;
+    }
+    *out = g_scratch[device];
+    return PHMM_OK;
+}
+
 static int create_impl(phmm_ctx* c, int device)
 {
     int ndev = 0;
@@ -229,6 +262,9 @@ static int create_impl(phmm_ctx* c, int device)
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, long_kernel_ptr(q == 0), kWave, 0));
         c->grid_long[q] = std::max(1, per_cu) * c->cus;
     }
+    void* sp = nullptr;  // this device's scratch address, for phmm_forward_batch_noalloc
+    const int rc = scratch_for(device, &sp);
+    if (rc != PHMM_OK) return rc;
     return build_tables(c);
 }
 
@@ -262,12 +298,21 @@ static uint64_t pack_blocks(uint64_t n_pairs) { return (n_pairs + kPackBlock - 1
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static Layout layout_for(const phmm_ctx* c, uint64_t n_pairs)
+// Long-kernel grid of precision q (0 FP32, 1 FP64), capped at long_cap
+// wavefronts when long_cap > 0.  The ring slots of the workspace follow the
+// grid, so the workspace layout and the launches must use the same cap.
+static int long_grid(const phmm_ctx* c, int q, int long_cap)
+{
+    return long_cap > 0 ? std::min(c->grid_long[q], long_cap) : c->grid_long[q];
+}
+
+static Layout layout_for(const phmm_ctx* c, uint64_t n_pairs, int long_cap = 0)
 {
     Layout L;
     size_t o = 0;
     const uint64_t n = n_pairs ? n_pairs : 1;
-    const uint32_t slots = std::max(long_slots(c->grid_long[0]), long_slots(c->grid_long[1]));
+    const uint32_t slots = std::max(long_slots(long_grid(c, 0, long_cap)),
+                                    long_slots(long_grid(c, 1, long_cap)));
     L.ctr = o; o = align256(o + sizeof(Counters));
     L.chunk_info = o; o = align256(o + n * 4);
     L.blk_cnt = o; o = align256(o + pack_blocks(n) * kSeg * 4);
@@ -294,9 +339,9 @@ extern "C" size_t phmm_workspace_bytes(phmm_ctx* c, uint64_t n_pairs, uint32_t m
     return layout_for(c, n_pairs).total;
 }
 
-static Work work_for(phmm_ctx* c, void* ws, uint64_t n_pairs)
+static Work work_for(phmm_ctx* c, void* ws, uint64_t n_pairs, int long_cap = 0)
 {
-    Layout L = layout_for(c, n_pairs);
+    Layout L = layout_for(c, n_pairs, long_cap);
     char* base = static_cast<char*>(ws);
     Work w;
     w.ctr = reinterpret_cast<Counters*>(base + L.ctr);
@@ -346,14 +391,14 @@ static bool class_used(const Policy& pol, int cls)
 }
 
 static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s, uint32_t max_hap_len,
-                   uint32_t max_read_len)
+                   uint32_t max_read_len, int long_cap = 0)
 {
     const Policy pol = batch_policy(c, b.n_pairs, max_hap_len);
     Tables t;
     t.p64 = c->d_p64;
     t.pw64 = c->d_pw64;
     t.pw32 = c->d_pw32;
-    const Work w = work_for(c, ws, b.n_pairs);
+    const Work w = work_for(c, ws, b.n_pairs, long_cap);
     const bool timed = c->opt.timing != 0;
     if (timed) HIP_TRY(hipEventRecord(c->ev[0], s));
     hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, s, w.ctr);
@@ -402,8 +447,9 @@ static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s, uint32_
                              s, b, t, w, pol);
         if (timed) HIP_TRY(hipEventRecord(c->ev[3], s));
         const bool no_long = max_hap_len <= kShortMaxCols && max_read_len <= pol.fp32_max_rows;
-        const int lgrid[2] = {small && no_long ? std::min(c->grid_long[0], c->cus) : c->grid_long[0],
-                              small && no_long ? std::min(c->grid_long[1], c->cus) : c->grid_long[1]};
+        const int g0 = long_grid(c, 0, long_cap), g1 = long_grid(c, 1, long_cap);
+        const int lgrid[2] = {small && no_long ? std::min(g0, c->cus) : g0,
+                              small && no_long ? std::min(g1, c->cus) : g1};
         launch_long(s, lgrid, b, t, w, pol);
     } else if (timed) {
         HIP_TRY(hipEventRecord(c->ev[2], s));
@@ -485,7 +531,7 @@ static int enqueue_sync(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s,
 
 // Checks a device batch and fills the kernels' view of it.
 static int device_batch(phmm_ctx* c, const phmm_device_batch* db, double* d_out, uint8_t* d_flags,
-                        void* d_ws, size_t ws_bytes, Batch* b)
+                        void* d_ws, size_t ws_bytes, Batch* b, int long_cap = 0)
 {
     if (!c || !db) return fail(PHMM_EINVAL, "phmm_forward_batch_async: ctx or batch is NULL");
     if (db->n_pairs > 0xffffffffull) return fail(PHMM_ERANGE, "n_pairs exceeds 2^32-1");
@@ -497,7 +543,7 @@ static int device_batch(phmm_ctx* c, const phmm_device_batch* db, double* d_out,
         return fail(PHMM_ERANGE, "max_read_len %u exceeds %u", db->max_read_len, PHMM_MAX_READ);
     if (db->max_hap_len > PHMM_MAX_HAP)
         return fail(PHMM_ERANGE, "max_hap_len %u exceeds %u", db->max_hap_len, PHMM_MAX_HAP);
-    const size_t need = phmm_workspace_bytes(c, db->n_pairs, db->max_read_len, db->max_hap_len);
+    const size_t need = layout_for(c, db->n_pairs, long_cap).total;
     if (ws_bytes < need) return fail(PHMM_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
     b->reads = db->reads;
     b->bq = db->base_quals;
@@ -524,6 +570,28 @@ extern "C" int phmm_forward_batch_async(phmm_ctx* c, const phmm_device_batch* db
     HIP_TRY(hipSetDevice(c->device));
     return enqueue(c, b, d_ws, static_cast<hipStream_t>(hip_stream), db->max_hap_len,
                    db->max_read_len);
+}
+
+extern "C" int phmm_forward_batch_noalloc(phmm_ctx* c, const phmm_device_batch* db,
+                                          double* d_out, uint8_t* d_flags, void* hip_stream)
+{
+    if (!c || !db) return fail(PHMM_EINVAL, "phmm_forward_batch_noalloc: ctx or batch is NULL");
+    if (db->n_pairs > PHMM_NOALLOC_MAX_PAIRS)
+        return fail(PHMM_ERANGE, "phmm_forward_batch_noalloc: %llu pairs exceed the limit of %u",
+                    (unsigned long long)db->n_pairs, PHMM_NOALLOC_MAX_PAIRS);
+    const size_t need = layout_for(c, db->n_pairs, kNoAllocLongGrid).total;
+    if (need > kScratchBytes)
+        return fail(PHMM_ERANGE, "phmm_forward_batch_noalloc: needs %zu bytes of scratch, %zu held",
+                    need, kScratchBytes);
+    HIP_TRY(hipSetDevice(c->device));
+    void* ws = nullptr;
+    int rc = scratch_for(c->device, &ws);  // set at phmm_create; no lookup here normally
+    if (rc != PHMM_OK) return rc;
+    Batch b;
+    rc = device_batch(c, db, d_out, d_flags, ws, need, &b, kNoAllocLongGrid);
+    if (rc != PHMM_OK) return rc;
+    return enqueue(c, b, ws, static_cast<hipStream_t>(hip_stream), db->max_hap_len,
+                   db->max_read_len, kNoAllocLongGrid);
 }
 
 int phmm::forward_device_batch_sync(phmm_ctx* c, const phmm_device_batch* db, double* d_out,
