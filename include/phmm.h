@@ -261,6 +261,23 @@ int phmm_forward_batch_async(phmm_ctx* ctx, const phmm_device_batch* b, double* 
                              void* hip_stream);
 
 /*
+ * phmm_forward_batch_async replayed from a HIP graph: the same launches and
+ * results (bit-identical), captured once per distinct (batch pointers and
+ * size, workspace, length bounds, options) and replayed by one
+ * hipGraphLaunch on hip_stream afterwards.  The context keeps the graphs of
+ * its last four such keys; a new key of the same launch shape updates the
+ * least recently used graph's kernel parameters in place, another shape
+ * replaces it.  The graph reads the batch through its pointers when it runs,
+ * so new contents in the same buffers need no new capture.  The graph holds
+ * kernel nodes only (the counters are cleared by a kernel, not a memset).
+ * Timing (options.timing) is not recorded on this path.  Same arguments,
+ * ownership and errors as phmm_forward_batch_async.
+ */
+int phmm_forward_batch_graph(phmm_ctx* ctx, const phmm_device_batch* b, double* d_out_log10,
+                             uint8_t* d_flags, void* d_workspace, size_t ws_bytes,
+                             void* hip_stream);
+
+/*
  * phmm_forward_batch_async without a workspace argument, for callers that
  * cannot allocate device memory: code being captured into a HIP graph, tight
  * serving loops, harnesses that forbid hipMalloc.  The call allocates

@@ -11,7 +11,7 @@ from ._binding import (  # noqa: F401
     PHMM_FLAG_RESCALED, PHMM_FLAG_FP64, PHMM_PENDING, PhmmError, Context, Server, lib, lib_path,
     phmm_num_classes, phmm_class_n, phmm_validate_batch, phmm_forward_batch,
     phmm_forward_one, phmm_workspace_bytes, phmm_forward_batch_async, phmm_device_status,
-    phmm_forward_batch_noalloc,
+    phmm_forward_batch_noalloc, phmm_forward_batch_graph,
     phmm_last_counts, phmm_last_timing, phmm_vector_peak, phmm_copy_calib, DeviceBatch,
     genotype_offsets, phmm_genotype_batch, phmm_genotype_batch_async,
 )

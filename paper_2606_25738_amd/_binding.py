@@ -134,6 +134,8 @@ def lib():
             L.phmm_workspace_bytes.restype = ctypes.c_size_t
             L.phmm_forward_batch_async.argtypes = [vp, ctypes.POINTER(_DeviceBatch), vp, vp, vp,
                                                    ctypes.c_size_t, vp]
+            L.phmm_forward_batch_graph.argtypes = [vp, ctypes.POINTER(_DeviceBatch), vp, vp, vp,
+                                                   ctypes.c_size_t, vp]
             L.phmm_forward_batch_noalloc.argtypes = [vp, ctypes.POINTER(_DeviceBatch), vp, vp, vp]
             L.phmm_device_status.argtypes = [vp, vp]
             L.phmm_last_counts.argtypes = [vp, vp, ctypes.POINTER(_Counts)]
@@ -375,6 +377,16 @@ def phmm_forward_batch_async(ctx: Context, db: DeviceBatch, out, flags, workspac
     else:
         h = stream
     _check(lib().phmm_forward_batch_async(
+        ctx.handle, ctypes.byref(s), out.data_ptr(),
+        flags.data_ptr() if flags is not None else None, workspace.data_ptr(),
+        workspace.numel() * workspace.element_size(), h))
+
+
+def phmm_forward_batch_graph(ctx: Context, db: DeviceBatch, out, flags, workspace, stream=None):
+    """phmm_forward_batch_async replayed from the context's captured HIP graphs."""
+    s = db.struct()
+    h = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    _check(lib().phmm_forward_batch_graph(
         ctx.handle, ctypes.byref(s), out.data_ptr(),
         flags.data_ptr() if flags is not None else None, workspace.data_ptr(),
         workspace.numel() * workspace.element_size(), h))

@@ -86,6 +86,24 @@ extern "C" void phmm_default_options(phmm_options* o)
 }
 
 // ---------------------------------------------------------------- context
+// Everything one asynchronous pass's launches depend on: the batch's device
+// pointers and size, the workspace, the length bounds and the policy (which
+// includes the cost table).  Equal keys give identical launch sequences, so a
+// captured graph of one is a replay of the other.  Compared bytewise: built
+// from a zeroed object so that padding compares equal.
+struct GraphKey {
+    Batch b;
+    const void* ws;
+    uint32_t max_hap_len, max_read_len;
+    Policy pol;
+};
+struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+};
+constexpr int kGraphSlots = 4;
+
 struct phmm_ctx {
     int device = 0;
     phmm_options opt{};
@@ -111,6 +129,11 @@ struct phmm_ctx {
     // relative cost of one wavefront-row per (precision, class): N + 3 until
     // phmm_autotune or phmm_set_class_costs replaces it
     float cost[2][kNumClasses] = {};
+    // phmm_forward_batch_graph: captured launch sets, least recently used
+    // replaced first, and the stream they are captured on
+    GraphEntry graphs[kGraphSlots];
+    uint64_t graph_tick = 0;
+    hipStream_t cap_stream = nullptr;
 };
 
 static Policy make_policy(const phmm_options& o, const float (&cost)[2][kNumClasses])
@@ -192,6 +215,9 @@ extern "C" void phmm_destroy(phmm_ctx* c)
     for (auto& e : c->ev_chunk)
         if (e) (void)hipEventDestroy(e);
     if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
+    for (auto& g : c->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -391,7 +417,7 @@ static bool class_used(const Policy& pol, int cls)
 }
 
 static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s, uint32_t max_hap_len,
-                   uint32_t max_read_len, int long_cap = 0)
+                   uint32_t max_read_len, int long_cap = 0, bool allow_timing = true)
 {
     const Policy pol = batch_policy(c, b.n_pairs, max_hap_len);
     Tables t;
@@ -399,7 +425,7 @@ static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s, uint32_
     t.pw64 = c->d_pw64;
     t.pw32 = c->d_pw32;
     const Work w = work_for(c, ws, b.n_pairs, long_cap);
-    const bool timed = c->opt.timing != 0;
+    const bool timed = allow_timing && c->opt.timing != 0;
     if (timed) HIP_TRY(hipEventRecord(c->ev[0], s));
     hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, s, w.ctr);
     if (b.n_pairs > 0) launch_pack(s, b, w, pol);
@@ -592,6 +618,77 @@ extern "C" int phmm_forward_batch_noalloc(phmm_ctx* c, const phmm_device_batch* 
     if (rc != PHMM_OK) return rc;
     return enqueue(c, b, ws, static_cast<hipStream_t>(hip_stream), db->max_hap_len,
                    db->max_read_len, kNoAllocLongGrid);
+}
+
+// The asynchronous pass replayed from a HIP graph.  A context keeps the
+// launch sets of its last kGraphSlots distinct (batch, workspace, bounds,
+// policy) keys as instantiated graphs; a call with a known key is one
+// hipGraphLaunch.  A new key is captured on the context's capture stream
+// (the counter reset is a kernel, so the graph holds kernel nodes only) and
+// either updated into the least recently used graph, when the launch
+// sequence has the same shape, or instantiated in its place.
+extern "C" int phmm_forward_batch_graph(phmm_ctx* c, const phmm_device_batch* db, double* d_out,
+                                        uint8_t* d_flags, void* d_ws, size_t ws_bytes,
+                                        void* hip_stream)
+{
+    Batch b;
+    int rc = device_batch(c, db, d_out, d_flags, d_ws, ws_bytes, &b);
+    if (rc != PHMM_OK) return rc;
+    HIP_TRY(hipSetDevice(c->device));
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    GraphKey key;
+    memset(&key, 0, sizeof key);
+    key.b = b;
+    key.ws = d_ws;
+    key.max_hap_len = db->max_hap_len;
+    key.max_read_len = db->max_read_len;
+    key.pol = batch_policy(c, b.n_pairs, db->max_hap_len);
+    c->timed = false;
+    for (GraphEntry& e : c->graphs)
+        if (e.exec && memcmp(&e.key, &key, sizeof key) == 0) {
+            e.used = ++c->graph_tick;
+            HIP_TRY(hipGraphLaunch(e.exec, s));
+            return PHMM_OK;
+        }
+    if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    rc = enqueue(c, b, d_ws, c->cap_stream, db->max_hap_len, db->max_read_len, 0, false);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+    if (rc != PHMM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (ec != hipSuccess || !g)
+        return fail(PHMM_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+    GraphEntry* e = &c->graphs[0];
+    for (GraphEntry& x : c->graphs)
+        if (x.used < e->used) e = &x;
+    bool updated = false;
+    if (e->exec) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res;
+        if (hipGraphExecUpdate(e->exec, g, &bad, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+            updated = true;
+        } else {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(e->exec);
+            e->exec = nullptr;
+        }
+    }
+    if (!updated) {
+        const hipError_t ei = hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            e->exec = nullptr;
+            (void)hipGraphDestroy(g);
+            return fail(PHMM_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+        }
+    }
+    (void)hipGraphDestroy(g);
+    e->key = key;
+    e->used = ++c->graph_tick;
+    HIP_TRY(hipGraphLaunch(e->exec, s));
+    return PHMM_OK;
 }
 
 int phmm::forward_device_batch_sync(phmm_ctx* c, const phmm_device_batch* db, double* d_out,
