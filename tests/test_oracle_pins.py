@@ -143,6 +143,29 @@ def test_p4_phred_entry_matches_eq3():
     assert lg == pytest.approx(math.log10(want), abs=1e-14)
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_p4_zero_start_gives_zero_likelihood(seed):
+    """eq.1-2: row 1 is M(1,j) = P(r_1|h_j) T_DM_1 D(0,j-1), I(1,j) = 0, and
+    every later cell descends from row 1, so L = 0 exactly when T_DM_1 = 0
+    (gap byte 0 on the first read position), whatever the other rows hold;
+    a gap byte of 0 on any other row leaves L > 0."""
+    rng = np.random.default_rng(440 + seed)
+    l, k = int(rng.integers(1, 30)), int(rng.integers(1, 40))
+    read = bytes(rng.choice(np.frombuffer(b"ACGTN", np.uint8), l))
+    hap = bytes(rng.choice(np.frombuffer(b"ACGTN", np.uint8), k))
+    q = [rng.integers(0, 60, l).astype(np.uint8) for _ in range(3)]
+    g = rng.integers(1, 60, l).astype(np.uint8)
+    g0 = g.copy()
+    g0[0] = 0
+    lg, S, E = oracle.forward_one(read, q[0], q[1], q[2], g0, hap)
+    assert S == 0.0 and lg == -math.inf
+    if l > 1:
+        g1 = g.copy()
+        g1[int(rng.integers(1, l))] = 0
+        lg, S, E = oracle.forward_one(read, q[0], q[1], q[2], g1, hap)
+        assert S > 0.0 and math.isfinite(lg)
+
+
 # ---------------------------------------------------------------- P5
 @pytest.mark.parametrize("seed", range(5))
 def test_p5_ungapped_limit(seed):
