@@ -58,15 +58,36 @@ def _oracle_chunk(idx):
 
 
 def _cpu_model():
-    """The host CPU's model name (first entry of /proc/cpuinfo), or None."""
+    """The host CPU's model name as lscpu and /proc/cpuinfo report it (either
+    may be shortened inside a container), or None."""
+    names = []
+    try:
+        import subprocess
+        r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10)
+        for line in r.stdout.splitlines():
+            if line.strip().startswith("Model name"):
+                names.append(line.split(":", 1)[1].strip())
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
                 if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                    names.append(line.split(":", 1)[1].strip())
+                    break
     except OSError:
         pass
-    return None
+    names = list(dict.fromkeys(n for n in names if n))
+    return max(names, key=len) if names else None
+
+
+def _host_cpus():
+    """Logical CPUs of the host and those this process may run on."""
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = None
+    return os.cpu_count(), aff
 
 
 def sample_regions(batch, n_regions, seed=123):
@@ -268,6 +289,76 @@ def summarize_counters(pmc_csv, bench_json, out_path, commands):
               "- clock_ghz: %.3f" % (tot["GRBM_GUI_ACTIVE"] / 8.0 / max(1, ns)),
               "- pass_ms_under_counters: %.2f" % (ns / 1e6),
               "- sources_sha256: %s" % sources_digest(), ""]
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+LONG_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_WAVES", "SQ_WAVE_CYCLES",
+                 "SQ_BUSY_CU_CYCLES", "SQ_WAIT_ANY", "GRBM_GUI_ACTIVE")
+LONG_COUNTERS_PROFILE = os.path.join(ROOT, "profiles", "long_kernels_counters.md")
+
+
+def summarize_long_counters(pmc_csv, sweep_json, out_path, commands):
+    """Writes the instruction-count profile of the long-pair kernels from one
+    rocprofv3 --pmc run of `bench.py --sweep` over the lengths it names (the
+    JSON line gives each length's cells).  For each length and precision the
+    counters of the timed passes' long-kernel dispatches are averaged per
+    pass; VALU per CU-clock = SQ_INSTS_VALU / SQ_BUSY_CU_CYCLES, resident waves
+    per SIMD = SQ_WAVE_CYCLES / SQ_BUSY_CU_CYCLES / 4."""
+    rec = None
+    with open(sweep_json) as fh:
+        for line in fh:
+            if line.startswith("{"):
+                rec = json.loads(line)
+    rows = rec["sweep"]
+    by = {}
+    with open(pmc_csv, newline="") as fh:
+        for r in csv.DictReader(fh):
+            m = re.search(r"long_kernel<(float|double)>", r["Kernel_Name"])
+            if not m:
+                continue
+            d = by.setdefault(int(r["Dispatch_Id"]), dict(
+                prec="fp32" if m.group(1) == "float" else "fp64",
+                ns=int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+            d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    disp = [by[i] for i in sorted(by)]
+    # dispatches in sweep order: per length, the FP32 mode's passes, then the
+    # FP64 mode's; each pass launches the long kernel of its precision once
+    lines = ["# Instruction counts of the long-pair kernels, equal-length pairs", "",
+             "Commands (repository root, one MI355X):", ""]
+    lines += ["    " + c for c in commands]
+    lines += ["", "Workload: the length sweep's batches (one read of L bases against 16 haplotypes"
+              " of L bases per region); counters per pass of `long_kernel<float>` (FP32 mode) and"
+              " `long_kernel<double>` (FP64 mode), averaged over the passes of the run.", "",
+              "| L | kernel | pairs | tiles/pair | ms | GCUPS | VALU per cell | SALU per cell |"
+              " LDS per cell | VALU per CU-clock | waves per SIMD | wait share | clock GHz |",
+              "|---:|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    k = 0
+    per = {}
+    for row in rows:
+        for mode in ("fp32", "fp64"):
+            n_pass = 1 + int(rec.get("reps", 1))
+            ds = []
+            while k < len(disp) and len(ds) < n_pass:
+                ds.append(disp[k])
+                k += 1
+            if not ds:
+                continue
+            t = {c: sum(d.get(c, 0.0) for d in ds) / len(ds) for c in LONG_COUNTERS}
+            ns = sum(d["ns"] for d in ds) / len(ds)
+            cells = row["cells"]
+            busy = max(1.0, t["SQ_BUSY_CU_CYCLES"])
+            per[(row["length"], mode)] = t
+            lines.append("| %d | %s | %d | %d | %.2f | %.0f | %.2f | %.3f | %.3f | %.3f | %.2f | %.2f | %.2f |" % (
+                row["length"], ds[0]["prec"], row["pairs"], -(-row["length"] // 1024), ns / 1e6,
+                cells / ns, 64.0 * t["SQ_INSTS_VALU"] / cells, 64.0 * t["SQ_INSTS_SALU"] / cells,
+                64.0 * t["SQ_INSTS_LDS"] / cells, t["SQ_INSTS_VALU"] / busy,
+                t["SQ_WAVE_CYCLES"] / busy / 4.0, t["SQ_WAIT_ANY"] / max(1.0, t["SQ_WAVE_CYCLES"]),
+                t["GRBM_GUI_ACTIVE"] / 8.0 / max(1.0, ns)))
+    lines += ["", "VALU, SALU and LDS are lane-instructions per useful cell (wave-instructions x 64 /"
+              " cells); the wait share is SQ_WAIT_ANY / SQ_WAVE_CYCLES (wave-cycles spent waiting"
+              " on anything).", "", "- sources_sha256: %s" % sources_digest(), ""]
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines))
     print("\n".join(lines))
@@ -488,7 +579,7 @@ def sweep_leg(phmm, torch, args):
     around the whole pass, packer included) in the default FP32 + rerun mode
     and in plain FP64, best of `--sweep-reps` passes after one warm-up."""
     rows = []
-    for L in SWEEP_LENGTHS:
+    for L in args.sweep_lengths or SWEEP_LENGTHS:
         regions = max(1, min(1_000_000, int(math.ceil(args.sweep_cells / (16.0 * L * L)))))
         b = synth.generate(synth.sweep_cfg(L, regions))
         cells = int(pair_cells(b)[0].sum())
@@ -595,6 +686,73 @@ def one_pair_per_wave_leg(phmm, torch, args, costs):
     return res
 
 
+LONG_GOLDEN = os.path.join(ROOT, "tests", "golden", "long_reads_all.json")
+
+
+def long_reads_leg(phmm, torch, args):
+    """The long-read workload: 96 pairs, 32 each of 10,000, 32,000 and 100,000
+    base reads against haplotypes 1.1 times as long (5% substitutions, 2%
+    indels of 1-10 bp, Phred 5-30, ins/del 30, gcp 10), one pass over all of
+    them and one per length class: kernel-only GCUPS (HIP events, best of
+    `--long-reps` after a warm-up), the fraction of the vector roofline of
+    the precision each class runs in, and every result's error against the
+    oracle values stored by tests/golden/make_long_reads_all.py."""
+    with open(LONG_GOLDEN) as fh:
+        gold = json.load(fh)["pairs"]
+    want = np.array([float(g["log10_l"]) for g in gold])
+    b = synth.generate("long_reads")
+    cells_pp, rl, hl = pair_cells(b)
+    assert np.array_equal(rl, [g["read_len"] for g in gold]) and \
+        np.array_equal(hl, [g["hap_len"] for g in gold])
+    res = {"pairs": len(gold), "cells": int(cells_pp.sum())}
+
+    def one_pass(bb, cells):
+        db = phmm.DeviceBatch(bb, "cuda:0")
+        n = db.n_pairs
+        out = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        fl = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+        with phmm.Context(timing=True) as ctx:
+            ws = torch.empty(phmm.phmm_workspace_bytes(ctx, n, db.max_read_len, db.max_hap_len),
+                             dtype=torch.uint8, device="cuda:0")
+            stream = torch.cuda.Stream()
+            best = None
+            for r in range(1 + args.long_reps):
+                phmm.phmm_forward_batch_async(ctx, db, out, fl, ws, stream)
+                t = phmm.phmm_last_timing(ctx)["total_ms"]
+                if r > 0:
+                    best = t if best is None else min(best, t)
+            phmm.phmm_device_status(ctx, ws)
+        return best, out.cpu().numpy(), fl.cpu().numpy()
+
+    ms, got, f = one_pass(b, res["cells"])
+    res["all"] = dict(ms=round(ms, 2), gcups=round(res["cells"] / ms / 1e6, 1))
+    classes = []
+    for L in (10000, 32000, 100000):
+        idx = np.nonzero(rl == L)[0]
+        sub = synth.subset_pairs(b, idx)
+        c = int(cells_pp[idx].sum())
+        cms, cgot, cf = one_pass(sub, c)
+        fp32 = bool(np.all(cf & 0x01))
+        peak = FP32_PEAK_TFLOPS if fp32 else FP32_PEAK_TFLOPS / 2
+        err = np.abs(got[idx] - want[idx])
+        classes.append(dict(read_len=L, pairs=len(idx), cells=c, ms=round(cms, 2),
+                            gcups=round(c / cms / 1e6, 1), precision="fp32" if fp32 else "fp64",
+                            roofline_frac=round(FLOPS_PER_CELL * c / (cms / 1e3) / (peak * 1e12), 4),
+                            max_err=float(err.max()), mean_err=float(err.mean()),
+                            bound=1e-4 if fp32 else 1e-10,
+                            ok=bool(err.max() <= (1e-4 if fp32 else 1e-10)),
+                            flags=sorted(set(int(x) for x in f[idx]))))
+        log("long reads %d bp: %d pairs, %.1f GCUPS (%s, %.1f%% of its roofline), max err %.3g"
+            % (L, len(idx), classes[-1]["gcups"], classes[-1]["precision"],
+               100 * classes[-1]["roofline_frac"], classes[-1]["max_err"]))
+    res["classes"] = classes
+    res["ok"] = all(c["ok"] for c in classes)
+    log("long-read workload: %d pairs, %.3g cells, %.1f GCUPS in one pass"
+        % (res["pairs"], res["cells"], res["all"]["gcups"]))
+    torch.cuda.empty_cache()
+    return res
+
+
 def small_batch_leg(phmm, torch, args):
     """Latency of one small batch (about 3550 short pairs, all at once): the
     whole pass on device-resident inputs (HIP events, packer included), and
@@ -619,6 +777,29 @@ def small_batch_leg(phmm, torch, args):
                 dev.append(t["total_ms"])
                 phases.append(t)
         phmm.phmm_device_status(ctx, ws)
+        # the same pass from stream launches and replayed from the context's
+        # captured HIP graph, both timed by events around the call on the
+        # stream (device) and by the host clock from the call to the end of
+        # a stream synchronisation (submission included)
+        launch = {}
+        for how, fn in (("stream_launches", phmm.phmm_forward_batch_async),
+                        ("graph_replay", phmm.phmm_forward_batch_graph)):
+            evs, walls = [], []
+            for r in range(5 + args.small_reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                t0 = time.perf_counter()
+                e0.record(stream)
+                fn(ctx, db, out, fl, ws, stream)
+                e1.record(stream)
+                stream.synchronize()
+                if r >= 5:
+                    walls.append((time.perf_counter() - t0) * 1e3)
+                    evs.append(e0.elapsed_time(e1))
+            launch[how] = dict(device_ms_median=round(float(np.median(evs)), 4),
+                               device_ms_min=round(min(evs), 4),
+                               call_to_done_ms_median=round(float(np.median(walls)), 4))
+        res["launch"] = launch
         host, sync = [], []
         for r in range(5 + args.small_reps):
             t0 = time.perf_counter()
@@ -631,6 +812,8 @@ def small_batch_leg(phmm, torch, args):
                sync_pass_ms_median=round(float(np.median(sync)), 4),
                host_to_host_ms_median=round(float(np.median(host)), 4),
                host_to_host_ms_min=round(min(host), 4), phases_ms_median=ph)
+    log("small batch: stream launches %s, graph replay %s" % (res["launch"]["stream_launches"],
+                                                               res["launch"]["graph_replay"]))
     log("small batch: %d pairs, %.3g cells: asynchronous pass %.3f ms (min %.3f), synchronising "
         "pass %.3f ms, host-to-host %.3f ms; asynchronous phases %s"
         % (n, cells, res["device_ms_median"], res["device_ms_min"], res["sync_pass_ms_median"],
@@ -727,7 +910,11 @@ def main():
                          "(0 skips it)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default pack cost model instead of measuring it")
-    ap.add_argument("--serve-seconds", type=float, default=20.0,
+    ap.add_argument("--long-reps", type=int, default=2,
+                    help="timed passes of the long-read leg (0: skip the leg)")
+    ap.add_argument("--long-reads", action="store_true",
+                    help="print only the long-read leg")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the served Poisson stream (0 = no serving leg)")
     ap.add_argument("--serve-loads", type=lambda v: [float(x) for x in v.split(",")],
                     default=[0.5, 0.8],
@@ -746,6 +933,10 @@ def main():
     ap.add_argument("--sweep-cells", type=float, default=1e11,
                     help="cells per length in the sweep (capped at 1,000,000 regions)")
     ap.add_argument("--sweep-reps", type=int, default=3)
+    ap.add_argument("--sweep-lengths", type=lambda v: [int(x) for x in v.split(",")], default=None,
+                    help="comma-separated lengths of the sweep (default: 32 ... 131072)")
+    ap.add_argument("--summarize-long-counters", nargs=2, metavar=("PMC_CSV", "SWEEP_JSON"),
+                    help="write profiles/long_kernels_counters.md from a --pmc run of --sweep")
     ap.add_argument("--small-batch", action="store_true",
                     help="run only the small-batch latency leg (about 3550 short pairs)")
     ap.add_argument("--small-reps", type=int, default=50,
@@ -769,6 +960,10 @@ def main():
         summarize_counters(args.summarize_counters[0], args.summarize_counters[1], COUNTERS_PROFILE,
                            args.command)
         return
+    if args.summarize_long_counters:
+        summarize_long_counters(args.summarize_long_counters[0], args.summarize_long_counters[1],
+                                LONG_COUNTERS_PROFILE, args.command)
+        return
     if args.summarize_traffic:
         summarize_traffic(args.summarize_traffic[0], args.summarize_traffic[1], TRAFFIC_PROFILE,
                           args.regions, args.calib_copy_mib, args.command)
@@ -783,11 +978,17 @@ def main():
         import paper_2606_25738_amd as phmm
         print(json.dumps({"small_batch": small_batch_leg(phmm, torch, args), "data": "synthetic"}))
         return
+    if args.long_reads:
+        import torch
+        import paper_2606_25738_amd as phmm
+        print(json.dumps({"long_reads": long_reads_leg(phmm, torch, args), "data": "synthetic"}))
+        return
     if args.sweep:
         import torch
         import paper_2606_25738_amd as phmm
         rows = sweep_leg(phmm, torch, args)
         print(json.dumps({"sweep": rows, "unit": "GCUPS (kernel-only)", "data": "synthetic",
+                          "reps": args.sweep_reps,
                           "workload": "equal-length pairs, 16 haplotypes per read"}))
         return
 
@@ -808,8 +1009,12 @@ def main():
         scells = int(cells_pp[sidx].sum())
         log("oracle on %d pairs (%d regions, %.3g cells), %d processes" % (len(sidx), nreg, scells, cores))
         ovals, wall, cpusec = run_oracle(batch, sidx, cores)
+        ncpu, naff = _host_cpus()
         cpu = dict(value=round(scells / wall / 1e9, 4), unit="GCUPS", cores=cores, kind="oracle",
-                   cpu_model=_cpu_model(), single_core_gcups=round(scells / cpusec / 1e9, 4),
+                   cpu_model=_cpu_model(), host_logical_cpus=ncpu, affinity_cpus=naff,
+                   cores_note="one single-threaded oracle process per logical CPU this process "
+                              "may run on, at most 16",
+                   single_core_gcups=round(scells / cpusec / 1e9, 4),
                    sample="%d random regions of the same workload (%d pairs, %.3g cells); "
                           "single-core %.3f GCUPS" % (nreg, len(sidx), scells,
                                                        scells / cpusec / 1e9),
@@ -935,6 +1140,7 @@ def main():
     opw = one_pair_per_wave_leg(phmm, torch, args, costs) if args.opw_regions > 0 else None
     uneven = batched_uneven_leg(phmm, torch, args) if args.uneven else None
     small = small_batch_leg(phmm, torch, args) if args.small_reps > 0 else None
+    long_reads = long_reads_leg(phmm, torch, args) if args.long_reps > 0 else None
     serving = serve_leg(phmm, args) if args.serve_seconds > 0 else None
 
     parity = None
@@ -967,7 +1173,8 @@ def main():
         pack_costs=None if costs is None else dict(fp32=np.round(costs[0], 3).tolist(),
                                                    fp64=np.round(costs[1], 3).tolist()),
         fp64_plain=fp64, fp64_one_pair_per_wave=opw, end_to_end=end_to_end,
-        batched_uneven=uneven, small_batch=small, parity_sample=parity, serving=serving,
+        batched_uneven=uneven, small_batch=small, long_reads=long_reads, parity_sample=parity,
+        serving=serving,
         genotype_likelihoods=genotype,
     )
     print(json.dumps(rec), flush=True)

@@ -106,10 +106,12 @@ typedef struct phmm_options {
                                rounding bias grows with the row count); default 2048 */
     uint32_t long_fp32_max_rows; /* long pairs (haplotype > 64 x 24) with reads up to
                                this many rows run in FP32 with rescaling, longer ones
-                               in FP64; default 32768.  The per-row coefficients are
-                               rounded to FP32 stochastically (unbiased, keyed by the
-                               row), which keeps the error within 1e-4 in log10 to
-                               about 32k rows (measured 1.3e-5 at 10k, 4.7e-5 at 32k). */
+                               in FP64; default PHMM_MAX_READ (every long pair in
+                               FP32).  The per-row coefficients are rounded to FP32
+                               stochastically (unbiased, keyed by the row) and each
+                               cell adds its gap terms before its match term, so
+                               rounding errors do not add up coherently along the
+                               read: within 1e-4 in log10 up to the longest reads    */
     uint32_t watchdog_spins;/* long kernel: polls of a neighbour tile before giving
                                up with PHMM_ETIMEOUT; 0 = default                     */
     int timing;             /* 1: record per-phase HIP events (phmm_last_timing)     */
@@ -463,6 +465,15 @@ typedef struct phmm_server_options {
     uint64_t hbm_budget_bytes;  /* device bytes for admitted work; default 24 GiB       */
     uint32_t max_batch_regions; /* regions per batch at most; default 8192              */
     uint32_t short_cu_percent;  /* 0 = no CU masks; else the short lanes' CU share      */
+    uint32_t long_read_min;     /* a region whose longest read exceeds this many bases
+                                   (or whose longest haplotype exceeds 64 x 24 columns)
+                                   queues for the long lanes; default 2048 (the FP32
+                                   row limit of the short kernels)                      */
+    uint32_t long_grid_percent; /* the long lanes' persistent grids as a share of a full
+                                   chip's, 1..100 (the long-pair kernels keep at least
+                                   1024 wavefronts): below 100 a long region's batch
+                                   leaves wavefront slots on every compute unit for the
+                                   short lanes' kernels; default 100                   */
 } phmm_server_options;
 
 typedef struct phmm_request_info {

@@ -64,7 +64,8 @@ class _Counts(ctypes.Structure):
 class _ServerOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("lanes", ctypes.c_uint32),
                 ("long_lanes", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64),
-                ("max_batch_regions", ctypes.c_uint32), ("short_cu_percent", ctypes.c_uint32)]
+                ("max_batch_regions", ctypes.c_uint32), ("short_cu_percent", ctypes.c_uint32),
+                ("long_read_min", ctypes.c_uint32), ("long_grid_percent", ctypes.c_uint32)]
 
 
 class _RequestInfo(ctypes.Structure):
@@ -474,7 +475,8 @@ class Server:
 
     def __init__(self, device: int = 0, precision: int = PHMM_FP32_RERUN, lanes: int | None = None,
                  long_lanes: int | None = None, hbm_budget_bytes: int | None = None,
-                 max_batch_regions: int | None = None, short_cu_percent: int | None = None):
+                 max_batch_regions: int | None = None, short_cu_percent: int | None = None,
+                 long_read_min: int | None = None, long_grid_percent: int | None = None):
         L = lib()
         o = _ServerOptions()
         L.phmm_server_default_options(ctypes.byref(o))
@@ -482,7 +484,8 @@ class Server:
         for k, v in (("lanes", lanes), ("long_lanes", long_lanes),
                      ("hbm_budget_bytes", hbm_budget_bytes),
                      ("max_batch_regions", max_batch_regions),
-                     ("short_cu_percent", short_cu_percent)):
+                     ("short_cu_percent", short_cu_percent), ("long_read_min", long_read_min),
+                     ("long_grid_percent", long_grid_percent)):
             if v is not None:
                 setattr(o, k, v)
         h = ctypes.c_void_p()

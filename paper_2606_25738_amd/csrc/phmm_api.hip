@@ -79,7 +79,7 @@ extern "C" void phmm_default_options(phmm_options* o)
     o->force_class = -1;
     o->one_pair_per_wave = 0;
     o->fp32_max_rows = 2048;
-    o->long_fp32_max_rows = 32768;
+    o->long_fp32_max_rows = PHMM_MAX_READ;
     o->watchdog_spins = 0;
     o->timing = 0;
     o->route_diverse_fp64 = 1;
@@ -292,6 +292,17 @@ static int create_impl(phmm_ctx* c, int device)
     const int rc = scratch_for(device, &sp);
     if (rc != PHMM_OK) return rc;
     return build_tables(c);
+}
+
+void phmm::scale_grids(phmm_ctx* c, int percent)
+{
+    if (!c || percent <= 0 || percent >= 100) return;
+    auto cut = [percent](int g) { return std::max(1, (int)((int64_t)g * percent / 100)); };
+    for (auto& kind : c->grid_short)
+        for (int& g : kind) g = cut(g);
+    // a long pair's tiles must all be resident together once its read is
+    // longer than 512 rows per resident wavefront
+    for (int& g : c->grid_long) g = std::min(g, std::max(cut(g), kMinLongGrid));
 }
 
 extern "C" int phmm_create(phmm_ctx** out, int device, const phmm_options* opt)

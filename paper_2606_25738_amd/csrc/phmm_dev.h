@@ -298,8 +298,13 @@ __device__ __forceinline__ void row_step(const R (&Mi)[N], const R (&Ii)[N], R (
         const R mprev = n == 0 ? Mleft : Mi[n - 1];
         const R iprev = n == 0 ? Ileft : Ii[n - 1];
         const R p = emit_sel(hc[n / 4], 8 * (n % 4) + bidx, c.pm, c.px);
-        const R x = SC ? fmaR(c.cd, T, fmaR(c.tmm, mprev, iprev))
-                       : fmaR(c.cd, T, fmaR(c.tim, iprev, c.tmm * mprev));
+        // The small gap terms are summed first and the dominant match term
+        // last, in one FMA with its exact product: added to an already
+        // rounded sum, a delete term under half an ulp would be dropped every
+        // time, a bias of about -3e-9 per row in FP32 (-1.3e-4 in log10 at
+        // 100,000 rows); added to the exact product it rounds without bias.
+        const R x = SC ? fmaR(c.tmm, mprev, fmaR(c.cd, T, iprev))
+                       : fmaR(c.tmm, mprev, fmaR(c.tim, iprev, c.cd * T));
         const R m = p * x;
         Mo[n] = m;
         Io[n] = SC ? fmaR(c.b, Ii[n], Mi[n]) : fmaR(c.b, Ii[n], c.a * Mi[n]);

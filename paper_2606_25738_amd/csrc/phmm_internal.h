@@ -123,6 +123,12 @@ namespace phmm {
 int forward_device_batch_sync(phmm_ctx* c, const phmm_device_batch* db, double* d_out,
                               uint8_t* d_flags, void* d_ws, size_t ws_bytes, hipStream_t s);
 
+// Caps every persistent grid of a context at percent % of a full chip's (the
+// long-pair kernels keep at least kMinLongGrid wavefronts).  Call before the
+// context's first batch: the workspace layout follows the long grids.
+void scale_grids(phmm_ctx* c, int percent);
+constexpr int kMinLongGrid = 1024;
+
 struct Policy {
     int precision;          // 0 FP32+rerun, 1 FP64 plain
     int force_class;        // -1 or class index

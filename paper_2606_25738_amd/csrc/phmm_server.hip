@@ -14,10 +14,13 @@
 // its lane's device block for the whole pass.
 //
 // Regions whose longest haplotype exceeds the short kernel's reach, or whose
-// longest read exceeds the FP32 row limit, are long regions.  With
+// longest read exceeds long_read_min bases, are long regions.  With
 // long_lanes > 0 they queue separately and only those lanes take them, so a
-// short region never waits behind a long one inside a batch.  Optional CU
-// masks give the short lanes and the long lanes disjoint compute units.
+// short region never waits behind a long one inside a batch, and the long
+// lanes' persistent grids are capped at long_grid_percent of the chip, so a
+// long batch leaves wavefront slots on every compute unit for the short
+// lanes' kernels.  Optional CU masks give the short lanes and the long lanes
+// disjoint compute units instead.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -125,6 +128,8 @@ extern "C" void phmm_server_default_options(phmm_server_options* o)
     o->hbm_budget_bytes = 24ull << 30;
     o->max_batch_regions = 8192;
     o->short_cu_percent = 0;
+    o->long_read_min = 2048;
+    o->long_grid_percent = 100;
 }
 
 void phmm_server::worker(Lane* lane, uint32_t lane_id)
@@ -309,10 +314,12 @@ extern "C" int phmm_server_create(phmm_server** out, int device, const phmm_serv
     phmm_server_default_options(&o);
     if (opt) o = *opt;
     if (o.lanes == 0 || o.lanes > 16 || o.long_lanes >= o.lanes || o.hbm_budget_bytes < (64ull << 20) ||
-        o.max_batch_regions == 0 || o.short_cu_percent > 100 ||
+        o.max_batch_regions == 0 || o.short_cu_percent > 100 || o.long_read_min == 0 ||
+        o.long_grid_percent == 0 || o.long_grid_percent > 100 ||
         (o.precision != PHMM_FP32_RERUN && o.precision != PHMM_FP64_PLAIN))
         return phmm::set_error(PHMM_EINVAL, "phmm_server_create: bad options (lanes 1..16, "
-                               "long_lanes < lanes, budget >= 64 MiB, short_cu_percent <= 100)");
+                               "long_lanes < lanes, budget >= 64 MiB, short_cu_percent <= 100, "
+                               "long_read_min >= 1, long_grid_percent 1..100)");
     auto* s = new phmm_server();
     s->device = device;
     s->opt = o;
@@ -330,6 +337,7 @@ extern "C" int phmm_server_create(phmm_server** out, int device, const phmm_serv
         phmm_default_options(&co);
         co.precision = o.precision;
         rc = phmm_create(&lane->ctx, device, &co);  // sets the error message itself
+        if (rc == PHMM_OK && lane->is_long) phmm::scale_grids(lane->ctx, (int)o.long_grid_percent);
         if (rc == PHMM_OK) rc = make_stream(device, lane->is_long, o.long_lanes ? o.short_cu_percent : 0,
                                             &lane->stream, &s->cu_mask_status);
         if (rc == PHMM_OK && hipMalloc(&lane->dev, per_lane) != hipSuccess)
@@ -370,7 +378,7 @@ extern "C" int phmm_server_submit(phmm_server* s, const uint8_t* reads, const ui
     r->np = n_pairs;
     r->max_l = ml;
     r->max_k = mk;
-    r->is_long = mk > phmm::kShortMaxCols || ml > 2048;
+    r->is_long = mk > phmm::kShortMaxCols || ml > s->opt.long_read_min;
     const BatchLayout L = layout_of(s->lanes[0]->ctx, r->rb, r->nr, r->hb, r->nh, r->np, ml, mk);
     if (L.total > s->lanes[0]->bytes)
         return phmm::set_error(PHMM_ENOMEM, "phmm_server_submit: region needs more device memory "

@@ -46,7 +46,7 @@ def need(cond: bool, what: str):
 
 class Policy:
     def __init__(self, precision=0, force_class=-1, one_pair_per_wave=False, fp32_max_rows=2048,
-                 long_fp32_max_rows=32768, route_diverse=True, cost=None):
+                 long_fp32_max_rows=131072, route_diverse=True, cost=None):
         self.precision = precision
         self.force_class = force_class
         self.one_pair_per_wave = one_pair_per_wave

@@ -52,7 +52,7 @@ def test_default_options():
     assert o.precision == phmm.PHMM_FP32_RERUN
     assert o.accept_min_sum == 1e-28
     assert o.force_class == -1 and o.one_pair_per_wave == 0
-    assert o.fp32_max_rows == 2048 and o.long_fp32_max_rows == 32768 and o.timing == 0
+    assert o.fp32_max_rows == 2048 and o.long_fp32_max_rows == 131072 and o.timing == 0
     assert o.route_diverse_fp64 == 1
 
 
@@ -189,7 +189,8 @@ def test_no_device_fails_loudly():
 
 def test_server_rejects_bad_options():
     for kw in (dict(lanes=0), dict(lanes=2, long_lanes=2), dict(hbm_budget_bytes=1 << 20),
-               dict(short_cu_percent=101), dict(precision=7)):
+               dict(short_cu_percent=101), dict(precision=7), dict(long_read_min=0),
+               dict(long_grid_percent=0), dict(long_grid_percent=101)):
         with pytest.raises(phmm.PhmmError) as e:
             phmm.Server(**kw)
         assert e.value.code == phmm.PHMM_EINVAL, kw

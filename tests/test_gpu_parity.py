@@ -427,8 +427,9 @@ def _golden_long(name):
 @pytest.mark.parametrize("name", ["long_read_100k", "max_read_131072"])
 def test_longest_reads_against_stored_oracle(ctx32, name):
     """The long-read workload's 100 kbp read (110 kbp haplotype) and a read at
-    the maximum length, 131,072 bases (144,179-base haplotype): FP64 long
-    kernel with rescaling, against oracle values stored by
+    the maximum length, 131,072 bases (144,179-base haplotype): FP32 long
+    kernel with rescaling (the default for every long pair), and for the
+    100 kbp read also the FP64 long kernel, against oracle values stored by
     tests/golden/make_long_reads.py (a minute or more of oracle time each)."""
     g = _golden_long(name)
     if name == "long_read_100k":
@@ -441,9 +442,36 @@ def test_longest_reads_against_stored_oracle(ctx32, name):
     say("%s: read %d, haplotype %d" % (name, g["read_len"], g["hap_len"]))
     out, fl = phmm.phmm_forward_batch(ctx32, b)
     want = float(g["log10_l"])
-    say("  log10 L = %.9f (oracle %.9f), flags 0x%02x" % (out[0], want, fl[0]))
-    assert fl[0] & phmm.PHMM_FLAG_LONG and fl[0] & phmm.PHMM_FLAG_FP64
-    assert abs(out[0] - want) <= TOL64
+    say("  FP32: log10 L = %.9f (oracle %.9f, error %.2e), flags 0x%02x"
+        % (out[0], want, out[0] - want, fl[0]))
+    assert fl[0] & phmm.PHMM_FLAG_LONG and fl[0] & phmm.PHMM_FLAG_FP32
+    assert abs(out[0] - want) <= TOL32
+    if name == "long_read_100k":
+        with phmm.Context(long_fp32_max_rows=32768) as c64:
+            out, fl = phmm.phmm_forward_batch(c64, b)
+        say("  FP64: log10 L = %.9f, error %.2e" % (out[0], out[0] - want))
+        assert fl[0] & phmm.PHMM_FLAG_LONG and fl[0] & phmm.PHMM_FLAG_FP64
+        assert abs(out[0] - want) <= TOL64
+
+
+def test_long_read_workload_against_stored_oracle(ctx32):
+    """All 96 pairs of the long-read workload (32 each of 10, 32 and 100 kbp
+    reads against haplotypes 1.1 times as long) in one batch, each against
+    the oracle value stored by tests/golden/make_long_reads_all.py: FP32 long
+    kernel within 1e-4 on every pair."""
+    import json
+    with open(os.path.join(ROOT, "tests", "golden", "long_reads_all.json")) as fh:
+        gold = json.load(fh)["pairs"]
+    b = synth.generate("long_reads")
+    assert [int(x) for x in np.diff(b["read_offsets"])] == [g["read_len"] for g in gold]
+    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    want = np.array([float(g["log10_l"]) for g in gold])
+    d = np.abs(out - want)
+    for c, L in enumerate((10000, 32000, 100000)):
+        say("long reads %d bp: max error %.2e, mean %.2e" % (L, d[32 * c:32 * c + 32].max(),
+                                                            d[32 * c:32 * c + 32].mean()))
+    assert np.all(fl & phmm.PHMM_FLAG_FP32) and np.all(fl & phmm.PHMM_FLAG_LONG)
+    assert d.max() <= TOL32
 
 
 def _async_pass(ctx, b):

@@ -27,13 +27,16 @@ def say(*a):
     print(*a, flush=True)
 
 
+LONG_READ_MIN = 2048  # the server's default routing bound
+
+
 @pytest.fixture(scope="module")
 def stream_regions():
     """A mixed stream: 160 regions of the served workload (short regions and
     long-read regions), cut short so the test stays quick."""
     b = synth.generate("served_stream", 0, 160)
     regs = [synth.region_slice(b, i) for i in range(160)]
-    nlong = sum(int(np.diff(r["read_offsets"]).max() > 2048 or
+    nlong = sum(int(np.diff(r["read_offsets"]).max() > LONG_READ_MIN or
                     np.diff(r["hap_offsets"]).max() > 1536) for r in regs)
     say("served stream sample: %d regions, %d long, %.3g cells" %
         (len(regs), nlong, sum(synth.batch_cells(r) for r in regs)))
@@ -80,9 +83,11 @@ def test_mix_equals_alone(stream_regions):
     for (a, fa), (b, fb, info) in zip(alone, got):
         compare(a, fa, b, fb, near=True)
         assert info["n_pairs"] == len(a) and info["latency_s"] >= info["queue_s"] >= 0
-    # the long lane took every long region
+    # the long lane took every long region (a read over 2048 bases or a
+    # haplotype over 64 x 24 columns, the server's defaults)
     for r, (_, _, info) in zip(regs, got):
-        is_long = (np.diff(r["read_offsets"]).max() > 2048 or np.diff(r["hap_offsets"]).max() > 1536)
+        is_long = (np.diff(r["read_offsets"]).max() > LONG_READ_MIN or
+                   np.diff(r["hap_offsets"]).max() > 1536)
         assert info["is_long"] == int(is_long)
         if is_long:
             assert info["lane"] == 2
@@ -103,6 +108,33 @@ def test_served_short_regions_match_oracle(stream_regions):
         fin = np.isfinite(want)
         d = np.abs(np.where(fin, out, 0) - np.where(fin, want, 0))
         is32 = (fl & phmm.PHMM_FLAG_FP32) != 0
+        assert d[is32].max(initial=0) <= TOL32 and d[~is32].max(initial=0) <= TOL64
+
+
+def test_served_long_regions_match_oracle(stream_regions):
+    """Long-read regions through the long lane (capped grids), with short
+    regions running beside them: sampled pairs of the shortest long regions
+    against the oracle."""
+    longs = [r for r in stream_regions if np.diff(r["read_offsets"]).max() > LONG_READ_MIN]
+    longs.sort(key=lambda r: int(np.diff(r["read_offsets"]).max()))
+    pick = longs[:3]
+    short = [r for r in stream_regions if np.diff(r["read_offsets"]).max() <= LONG_READ_MIN][:40]
+    assert pick and short
+    # long lanes on half the chip's persistent grid, regions over 512-base
+    # reads routed to them
+    with phmm.Server(lanes=3, long_lanes=1, hbm_budget_bytes=6 << 30, long_read_min=512,
+                     long_grid_percent=50) as srv:
+        ts = [srv.submit(r) for r in pick + short]
+        res = [srv.wait(t) for t in ts]
+    rng = np.random.default_rng(9)
+    for r, (out, fl, info) in zip(pick, res):
+        assert info["is_long"] == 1 and info["lane"] == 2
+        idx = np.sort(rng.choice(len(out), size=min(3, len(out)), replace=False))
+        say("served long region: read %d bases, %d pairs, checking %s" %
+            (int(np.diff(r["read_offsets"]).max()), len(out), idx.tolist()))
+        want = oracle.forward_pairs(r, idx, rescale=True)
+        d = np.abs(out[idx] - want)
+        is32 = (fl[idx] & phmm.PHMM_FLAG_FP32) != 0
         assert d[is32].max(initial=0) <= TOL32 and d[~is32].max(initial=0) <= TOL64
 
 
