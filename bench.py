@@ -305,7 +305,8 @@ def summarize_long_counters(pmc_csv, sweep_json, out_path, commands):
     JSON line gives each length's cells).  For each length and precision the
     counters of the timed passes' long-kernel dispatches are averaged per
     pass; VALU per CU-clock = SQ_INSTS_VALU / SQ_BUSY_CU_CYCLES, resident waves
-    per SIMD = SQ_WAVE_CYCLES / SQ_BUSY_CU_CYCLES / 4."""
+    per SIMD = SQ_WAVE_CYCLES / SQ_BUSY_CU_CYCLES (calibrated on the FP64 long
+    kernel, which holds exactly one wave per SIMD and reads 1.00)."""
     rec = None
     with open(sweep_json) as fh:
         for line in fh:
@@ -324,7 +325,11 @@ def summarize_long_counters(pmc_csv, sweep_json, out_path, commands):
             d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
     disp = [by[i] for i in sorted(by)]
     # dispatches in sweep order: per length, the FP32 mode's passes, then the
-    # FP64 mode's; each pass launches the long kernel of its precision once
+    # FP64 mode's; each pass launches both long kernels (the one of the other
+    # precision has no pairs), so per length and kernel the first passes are
+    # the FP32 mode's and the next the FP64 mode's
+    f32 = [d for d in disp if d["prec"] == "fp32"]
+    f64 = [d for d in disp if d["prec"] == "fp64"]
     lines = ["# Instruction counts of the long-pair kernels, equal-length pairs", "",
              "Commands (repository root, one MI355X):", ""]
     lines += ["    " + c for c in commands]
@@ -334,15 +339,12 @@ def summarize_long_counters(pmc_csv, sweep_json, out_path, commands):
               "| L | kernel | pairs | tiles/pair | ms | GCUPS | VALU per cell | SALU per cell |"
               " LDS per cell | VALU per CU-clock | waves per SIMD | wait share | clock GHz |",
               "|---:|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
-    k = 0
     per = {}
-    for row in rows:
+    n_pass = 1 + int(rec.get("reps", 1))
+    for li, row in enumerate(rows):
         for mode in ("fp32", "fp64"):
-            n_pass = 1 + int(rec.get("reps", 1))
-            ds = []
-            while k < len(disp) and len(ds) < n_pass:
-                ds.append(disp[k])
-                k += 1
+            src, first = (f32, 2 * li * n_pass) if mode == "fp32" else (f64, (2 * li + 1) * n_pass)
+            ds = src[first:first + n_pass]
             if not ds:
                 continue
             t = {c: sum(d.get(c, 0.0) for d in ds) / len(ds) for c in LONG_COUNTERS}
@@ -354,7 +356,7 @@ def summarize_long_counters(pmc_csv, sweep_json, out_path, commands):
                 row["length"], ds[0]["prec"], row["pairs"], -(-row["length"] // 1024), ns / 1e6,
                 cells / ns, 64.0 * t["SQ_INSTS_VALU"] / cells, 64.0 * t["SQ_INSTS_SALU"] / cells,
                 64.0 * t["SQ_INSTS_LDS"] / cells, t["SQ_INSTS_VALU"] / busy,
-                t["SQ_WAVE_CYCLES"] / busy / 4.0, t["SQ_WAIT_ANY"] / max(1.0, t["SQ_WAVE_CYCLES"]),
+                t["SQ_WAVE_CYCLES"] / busy, t["SQ_WAIT_ANY"] / max(1.0, t["SQ_WAVE_CYCLES"]),
                 t["GRBM_GUI_ACTIVE"] / 8.0 / max(1.0, ns)))
     lines += ["", "VALU, SALU and LDS are lane-instructions per useful cell (wave-instructions x 64 /"
               " cells); the wait share is SQ_WAIT_ANY / SQ_WAVE_CYCLES (wave-cycles spent waiting"
