@@ -452,7 +452,11 @@ def serve_leg(phmm, args):
     them continuously.  First the sustainable capacity is measured by
     submitting a block of regions at once, then one stream runs for
     args.serve_seconds at each fraction of that capacity in args.serve_loads
-    (fresh regions for each stream)."""
+    (fresh regions for each stream).  The server runs with its defaults
+    (long-read regions on a long lane whose grids are a quarter of the chip's,
+    so short regions never wait behind them); the same measurement with the
+    long lane on the whole chip (the throughput setting) follows, one stream
+    of args.serve_compare_seconds at 0.8 x its own capacity."""
     gen_chunk = 2000
     cache = {}
 
@@ -462,35 +466,42 @@ def serve_leg(phmm, args):
             cache[c] = synth.generate("served_stream", c * gen_chunk, gen_chunk)
         return synth.region_slice(cache[c], i - c * gen_chunk)
 
+    def run(opts, loads, seconds, first):
+        with phmm.Server(**opts) as srv:
+            # capacity: a block submitted at once
+            n_cap = args.serve_capacity_regions
+            regs = [region(first + i) for i in range(n_cap)]
+            t0 = time.perf_counter()
+            ts = [srv.submit(r) for r in regs]
+            cap_cells = 0
+            for t in ts:
+                _, _, info = srv.wait(t)
+                cap_cells += info["cells"]
+            span = time.perf_counter() - t0
+            cap_rps = n_cap / span
+            log("serving capacity (%s): %d regions, %.3g cells in %.2f s -> %.1f regions/s, %.1f GCUPS"
+                % (opts, n_cap, cap_cells, span, cap_rps, cap_cells / span / 1e9))
+            del regs
+            cache.clear()
+            streams = []
+            first += n_cap
+            for si, load in enumerate(loads):
+                streams.append(_serve_stream(srv, region, first, load, cap_rps, seconds, seed=4 + si))
+                first += streams[-1]["regions"]
+                cache.clear()
+        return dict(capacity_regions_per_s=round(cap_rps, 2),
+                    capacity_gcups=round(cap_cells / span / 1e9, 2), streams=streams), first
+
     opts = dict(lanes=args.serve_lanes, long_lanes=1, hbm_budget_bytes=args.serve_budget_gib << 30,
                 short_cu_percent=args.serve_short_cu)
-    with phmm.Server(**opts) as srv:
-        # capacity: a block submitted at once
-        n_cap = args.serve_capacity_regions
-        regs = [region(i) for i in range(n_cap)]
-        t0 = time.perf_counter()
-        ts = [srv.submit(r) for r in regs]
-        cap_cells = 0
-        for t in ts:
-            _, _, info = srv.wait(t)
-            cap_cells += info["cells"]
-        span = time.perf_counter() - t0
-        cap_rps = n_cap / span
-        log("serving capacity: %d regions, %.3g cells in %.2f s -> %.1f regions/s, %.1f GCUPS"
-            % (n_cap, cap_cells, span, cap_rps, cap_cells / span / 1e9))
-        del regs
-        cache.clear()
-        streams = []
-        first = n_cap
-        for si, load in enumerate(args.serve_loads):
-            streams.append(_serve_stream(srv, region, first, load, cap_rps, args.serve_seconds,
-                                         seed=4 + si))
-            first += streams[-1]["regions"]
-            cache.clear()
-    res = dict(arrival="poisson", capacity_regions_per_s=round(cap_rps, 2),
-               capacity_gcups=round(cap_cells / span / 1e9, 2), streams=streams,
+    main, first = run(opts, args.serve_loads, args.serve_seconds, 0)
+    res = dict(arrival="poisson", capacity_regions_per_s=main["capacity_regions_per_s"],
+               capacity_gcups=main["capacity_gcups"], streams=main["streams"],
                lanes=args.serve_lanes, long_lanes=1, short_cu_percent=args.serve_short_cu,
-               budget_gib=args.serve_budget_gib)
+               long_read_min=512, long_grid_percent=25, budget_gib=args.serve_budget_gib)
+    if args.serve_compare_seconds > 0:
+        alt, _ = run(dict(opts, long_grid_percent=100), [0.8], args.serve_compare_seconds, first)
+        res["throughput_setting"] = dict(long_grid_percent=100, **alt)
     return res
 
 
@@ -918,6 +929,8 @@ def main():
                     help="print only the long-read leg")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the served Poisson stream (0 = no serving leg)")
+    ap.add_argument("--serve-compare-seconds", type=float, default=20.0,
+                    help="served stream with the long lane on the whole chip (0 = skip)")
     ap.add_argument("--serve-loads", type=lambda v: [float(x) for x in v.split(",")],
                     default=[0.5, 0.8],
                     help="arrival rates of the streams as fractions of the measured serving "

@@ -467,13 +467,15 @@ typedef struct phmm_server_options {
     uint32_t short_cu_percent;  /* 0 = no CU masks; else the short lanes' CU share      */
     uint32_t long_read_min;     /* a region whose longest read exceeds this many bases
                                    (or whose longest haplotype exceeds 64 x 24 columns)
-                                   queues for the long lanes; default 2048 (the FP32
-                                   row limit of the short kernels)                      */
+                                   queues for the long lanes; default 512              */
     uint32_t long_grid_percent; /* the long lanes' persistent grids as a share of a full
                                    chip's, 1..100 (the long-pair kernels keep at least
                                    1024 wavefronts): below 100 a long region's batch
                                    leaves wavefront slots on every compute unit for the
-                                   short lanes' kernels; default 100                   */
+                                   short lanes' kernels.  Default 25: short regions
+                                   then never wait for long ones (p99 within 2x of p50
+                                   at 0.8x load), at about half the capacity of 100,
+                                   where long regions carry 98% of the cells          */
 } phmm_server_options;
 
 typedef struct phmm_request_info {

@@ -128,8 +128,8 @@ extern "C" void phmm_server_default_options(phmm_server_options* o)
     o->hbm_budget_bytes = 24ull << 30;
     o->max_batch_regions = 8192;
     o->short_cu_percent = 0;
-    o->long_read_min = 2048;
-    o->long_grid_percent = 100;
+    o->long_read_min = 512;
+    o->long_grid_percent = 25;
 }
 
 void phmm_server::worker(Lane* lane, uint32_t lane_id)

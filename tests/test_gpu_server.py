@@ -27,7 +27,7 @@ def say(*a):
     print(*a, flush=True)
 
 
-LONG_READ_MIN = 2048  # the server's default routing bound
+LONG_READ_MIN = 512  # the server's default routing bound
 
 
 @pytest.fixture(scope="module")
@@ -83,7 +83,7 @@ def test_mix_equals_alone(stream_regions):
     for (a, fa), (b, fb, info) in zip(alone, got):
         compare(a, fa, b, fb, near=True)
         assert info["n_pairs"] == len(a) and info["latency_s"] >= info["queue_s"] >= 0
-    # the long lane took every long region (a read over 2048 bases or a
+    # the long lane took every long region (a read over 512 bases or a
     # haplotype over 64 x 24 columns, the server's defaults)
     for r, (_, _, info) in zip(regs, got):
         is_long = (np.diff(r["read_offsets"]).max() > LONG_READ_MIN or
@@ -120,9 +120,8 @@ def test_served_long_regions_match_oracle(stream_regions):
     pick = longs[:3]
     short = [r for r in stream_regions if np.diff(r["read_offsets"]).max() <= LONG_READ_MIN][:40]
     assert pick and short
-    # long lanes on half the chip's persistent grid, regions over 512-base
-    # reads routed to them
-    with phmm.Server(lanes=3, long_lanes=1, hbm_budget_bytes=6 << 30, long_read_min=512,
+    # long lanes on half the chip's persistent grid
+    with phmm.Server(lanes=3, long_lanes=1, hbm_budget_bytes=6 << 30,
                      long_grid_percent=50) as srv:
         ts = [srv.submit(r) for r in pick + short]
         res = [srv.wait(t) for t in ts]
