@@ -255,8 +255,10 @@ size_t phmm_workspace_bytes(phmm_ctx* ctx, uint64_t n_pairs, uint32_t max_read_l
  * launches that only catch exceptions (pairs that do not fit that class,
  * FP32 rejects, and long pairs when max_hap_len <= 64 x 24 and max_read_len
  * <= fp32_max_rows) then get small grids.  Errors
- * detected on the device (watchdog) are reported by phmm_device_status()
- * after the stream has passed the call.
+ * detected on the device are reported by phmm_device_status() after the
+ * stream has passed the call: PHMM_ETIMEOUT (watchdog), PHMM_ERANGE (a
+ * haplotype longer than 64 x 24 bases in a batch whose max_hap_len says
+ * there is none; its likelihood is still computed, in FP64).
  */
 int phmm_forward_batch_async(phmm_ctx* ctx, const phmm_device_batch* b, double* d_out_log10,
                              uint8_t* d_flags, void* d_workspace, size_t ws_bytes,

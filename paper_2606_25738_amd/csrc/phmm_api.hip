@@ -24,9 +24,9 @@ const void* short_kernel_ptr(int kind, int cls);
 __global__ void reset_kernel(Counters* c);
 void launch_pack(hipStream_t s, const Batch& b, const Work& w, const Policy& pol);
 uint32_t scan_chunks(uint32_t n_pack_blocks);
-void launch_long(hipStream_t s, const int (&grid)[2], const Batch& b, const Tables& t,
+void launch_long(hipStream_t s, const int (&grid)[kLongLists], const Batch& b, const Tables& t,
                  const Work& w, const Policy& p);
-const void* long_kernel_ptr(bool fp32);
+const void* long_kernel_ptr(int q);
 int launch_genotype(hipStream_t s, int cus, const double* lk, uint64_t n_lk,
                     const uint64_t* lk_off, const uint32_t* n_reads, const uint32_t* n_haps,
                     const uint64_t* gl_off, uint32_t n_regions, double* gl, uint64_t n_gl,
@@ -110,7 +110,7 @@ struct phmm_ctx {
     hipStream_t stream = nullptr;
     int cus = 0;
     int grid_short[kNumKernelKinds][kNumClasses] = {};  // persistent wavefronts per kernel
-    int grid_long[2] = {};  // persistent wavefronts of the FP32 and FP64 long kernels
+    int grid_long[kLongLists] = {};  // persistent wavefronts of each list's long kernel
     double* d_p64 = nullptr;
     double* d_pw64 = nullptr;
     float* d_pw32 = nullptr;
@@ -283,9 +283,9 @@ static int create_impl(phmm_ctx* c, int device)
                 &per_cu, short_kernel_ptr(kind, cls), kWave, 0));
             c->grid_short[kind][cls] = std::max(1, per_cu) * c->cus;
         }
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < kLongLists; ++q) {
         int per_cu = 0;
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, long_kernel_ptr(q == 0), kWave, 0));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, long_kernel_ptr(q), kWave, 0));
         c->grid_long[q] = std::max(1, per_cu) * c->cus;
     }
     void* sp = nullptr;  // this device's scratch address, for phmm_forward_batch_noalloc
@@ -327,8 +327,8 @@ extern "C" int phmm_create(phmm_ctx** out, int device, const phmm_options* opt)
 
 // ---------------------------------------------------------------- workspace
 struct Layout {
-    size_t ctr, chunk_info, blk_cnt, blk_lc, chunk_part, packs, items, deferred, long_list32,
-        long_list64, long_pref, ring, slot, total;
+    size_t ctr, chunk_info, blk_cnt, blk_lc, chunk_part, packs, items, deferred,
+        long_pend[2], long_list[kLongLists], long_pref, ring, slot, total;
 };
 
 static uint64_t pack_blocks(uint64_t n_pairs) { return (n_pairs + kPackBlock - 1) / kPackBlock; }
@@ -348,8 +348,8 @@ static Layout layout_for(const phmm_ctx* c, uint64_t n_pairs, int long_cap = 0)
     Layout L;
     size_t o = 0;
     const uint64_t n = n_pairs ? n_pairs : 1;
-    const uint32_t slots = std::max(long_slots(long_grid(c, 0, long_cap)),
-                                    long_slots(long_grid(c, 1, long_cap)));
+    uint32_t slots = 0;
+    for (int q = 0; q < kLongLists; ++q) slots = std::max(slots, long_slots(long_grid(c, q, long_cap)));
     L.ctr = o; o = align256(o + sizeof(Counters));
     L.chunk_info = o; o = align256(o + n * 4);
     L.blk_cnt = o; o = align256(o + pack_blocks(n) * kSeg * 4);
@@ -358,8 +358,14 @@ static Layout layout_for(const phmm_ctx* c, uint64_t n_pairs, int long_cap = 0)
     L.packs = o; o = align256(o + n * sizeof(Pack));
     L.items = o; o = align256(o + n * sizeof(Item));
     L.deferred = o; o = align256(o + n * 4);
-    L.long_list32 = o; o = align256(o + n * 4);
-    L.long_list64 = o; o = align256(o + n * 4);
+    for (int q = 0; q < 2; ++q) {
+        L.long_pend[q] = o;
+        o = align256(o + n * 4);
+    }
+    for (int q = 0; q < kLongLists; ++q) {
+        L.long_list[q] = o;
+        o = align256(o + n * 4);
+    }
     L.long_pref = o; o = align256(o + (n + 1) * 4);
     L.ring = o; o = align256(o + (size_t)slots * long_ring_slot_bytes());
     L.slot = o; o = align256(o + (size_t)slots * 3 * sizeof(uint32_t));
@@ -391,8 +397,8 @@ static Work work_for(phmm_ctx* c, void* ws, uint64_t n_pairs, int long_cap = 0)
     w.packs = reinterpret_cast<Pack*>(base + L.packs);
     w.items = reinterpret_cast<Item*>(base + L.items);
     w.deferred = reinterpret_cast<uint32_t*>(base + L.deferred);
-    w.long_list[0] = reinterpret_cast<uint32_t*>(base + L.long_list32);
-    w.long_list[1] = reinterpret_cast<uint32_t*>(base + L.long_list64);
+    for (int q = 0; q < 2; ++q) w.long_pend[q] = reinterpret_cast<uint32_t*>(base + L.long_pend[q]);
+    for (int q = 0; q < kLongLists; ++q) w.long_list[q] = reinterpret_cast<uint32_t*>(base + L.long_list[q]);
     w.long_pref = reinterpret_cast<uint32_t*>(base + L.long_pref);
     w.long_ring = reinterpret_cast<double*>(base + L.ring);
     w.long_prog = reinterpret_cast<uint32_t*>(base + L.slot);
@@ -411,6 +417,7 @@ constexpr uint64_t kSmallBatchPairs = 8192;
 static Policy batch_policy(phmm_ctx* c, uint64_t n_pairs, uint32_t max_hap_len)
 {
     Policy pol = make_policy(c->opt, c->cost);
+    pol.long_haps = max_hap_len > kShortMaxCols ? 1 : 0;
     if (n_pairs <= kSmallBatchPairs && pol.force_class < 0) {
         const uint32_t k = std::max(1u, std::min(max_hap_len, kShortMaxCols));
         const int n = std::max(class_n(0), (int)((k + kWave - 1) / kWave));
@@ -483,10 +490,18 @@ static int enqueue(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s, uint32_
                                                                 : net(cap(c->grid_short[kAll64][cls]), 4),
                              s, b, t, w, pol);
         if (timed) HIP_TRY(hipEventRecord(c->ev[3], s));
-        const bool no_long = max_hap_len <= kShortMaxCols && max_read_len <= pol.fp32_max_rows;
-        const int g0 = long_grid(c, 0, long_cap), g1 = long_grid(c, 1, long_cap);
-        const int lgrid[2] = {small && no_long ? std::min(g0, c->cus) : g0,
-                              small && no_long ? std::min(g1, c->cus) : g1};
+        // Lists 0-2 are filled by the routing kernel only, with pairs whose
+        // haplotype exceeds the short kernels' reach; list 3 also takes FP64
+        // sums that underflowed (and long pairs that contradict the batch's
+        // length bound).  Without haplotypes that long only list 3 is
+        // launched, with one wavefront per CU in a small batch.
+        const bool no_long_haps = max_hap_len <= kShortMaxCols;
+        const bool no_long = no_long_haps && max_read_len <= pol.fp32_max_rows;
+        int lgrid[kLongLists];
+        for (int q = 0; q < kLongLists; ++q) {
+            const int g = long_grid(c, q, long_cap);
+            lgrid[q] = (no_long_haps && q != kLongLists - 1) ? 0 : small && no_long ? std::min(g, c->cus) : g;
+        }
         launch_long(s, lgrid, b, t, w, pol);
     } else if (timed) {
         HIP_TRY(hipEventRecord(c->ev[2], s));
@@ -553,8 +568,8 @@ static int enqueue_sync(phmm_ctx* c, const Batch& b, void* ws, hipStream_t s,
         }
         if (timed) HIP_TRY(hipEventRecord(c->ev[3], s));
         if ((rc = fetch()) != PHMM_OK) return rc;  // FP64 underflow adds long pairs
-        const int grid[2] = {h->n_long[0] > 0 ? c->grid_long[0] : 0,
-                             h->n_long[1] > 0 ? c->grid_long[1] : 0};
+        int grid[kLongLists];
+        for (int q = 0; q < kLongLists; ++q) grid[q] = h->n_long[q] > 0 ? c->grid_long[q] : 0;
         launch_long(s, grid, b, t, w, pol);
     } else if (timed) {
         HIP_TRY(hipEventRecord(c->ev[2], s));
@@ -719,7 +734,12 @@ extern "C" int phmm_device_status(phmm_ctx* c, void* d_ws)
     HIP_TRY(hipDeviceSynchronize());
     Counters h;
     HIP_TRY(hipMemcpy(&h, d_ws, sizeof h, hipMemcpyDeviceToHost));
-    if (h.status != 0) return fail((int)h.status, "device reported error %d", (int)h.status);
+    if (h.status != 0)
+        return fail((int)h.status, "device reported error %d%s", (int)h.status,
+                    (int)h.status == PHMM_ETIMEOUT ? " (long-pair watchdog)" : "");
+    if (h.bound_err != 0)
+        return fail(PHMM_ERANGE, "a haplotype longer than %u bases in a batch whose max_hap_len is at most %u",
+                    kShortMaxCols, kShortMaxCols);
     return PHMM_OK;
 }
 
@@ -738,9 +758,11 @@ extern "C" int phmm_last_counts(phmm_ctx* c, void* d_ws, phmm_counts* out)
     out->rerun_items = 0;  // one item per FP32 pack with a rejected pair
     for (int k = 0; k < kNumClasses; ++k) out->rerun_items += h.item_cnt[k];
     out->rerun_pairs = h.rerun_pairs;
-    out->long_pairs = (uint64_t)h.n_long[0] + h.n_long[1];
-    out->long_tiles = (uint64_t)h.long_tiles[0] + h.long_tiles[1];
-    out->long_pairs_fp32 = h.n_long[0];
+    for (int q = 0; q < kLongLists; ++q) {
+        out->long_pairs += h.n_long[q];
+        out->long_tiles += h.long_tiles[q];
+    }
+    out->long_pairs_fp32 = (uint64_t)h.n_long[0] + h.n_long[1];
     out->lane_columns = h.lane_columns;
     for (int k = 0; k < kNumClasses; ++k) out->deferred_packs += h.defer_cnt[k];
     return PHMM_OK;

@@ -33,6 +33,14 @@ constexpr int kPowStride = 66;
 // rows of boundary records buffered per tile.
 constexpr int kRing = 512;
 
+// Long-pair lists: q = 2 * precision + general.  [0] FP32 and [2] FP64 hold
+// pairs whose read has one gap byte (>= 1) on every row and insertion bytes
+// the scaled row form allows, run by a lean kernel without per-row gap
+// changes or the plain form; [1] FP32 and [3] FP64 hold the others (and the
+// FP64 pairs whose short-kernel sum underflowed).
+constexpr int kLongLists = 4;
+__host__ __device__ constexpr int long_list_of(int prec, bool general) { return 2 * prec + (general ? 1 : 0); }
+
 struct Pack {
     uint32_t pair_start;  // first pair (index into pair_list)
     uint32_t npairs;      // consecutive pairs, all of the same read
@@ -61,10 +69,12 @@ struct Counters {
     uint32_t item_cnt[kNumClasses];      // rerun items queued by the FP32 kernels
     uint32_t defer_cnt[kNumClasses];     // FP32 packs deferred to the general kernel
     uint32_t cursor[kNumKernelKinds][kNumClasses];  // next pack or item of each kernel
-    uint32_t n_long[2];                  // long pairs run in [0] FP32, [1] FP64
-    uint32_t long_tiles[2];
+    uint32_t n_pend[2];                  // long pairs per precision before routing
+    uint32_t n_long[kLongLists];         // long pairs per list (long_list_of)
+    uint32_t long_tiles[kLongLists];
     uint32_t long_cursor;
-    uint32_t status;                     // 0 or a PHMM_E* code (as uint32)
+    uint32_t status;                     // 0 or a PHMM_E* code (as uint32); stops the long kernels
+    uint32_t bound_err;                  // a long pair in a batch whose bound says none
     uint32_t rerun_pairs;                // counted by the FP64 kernel
     unsigned long long lane_columns;
 };
@@ -102,7 +112,8 @@ struct Work {
     Pack* packs;           // pack array, segments per (precision, class)
     Item* items;           // FP64 items, segments per class
     uint32_t* deferred;    // FP32 packs for the general kernel, segments per class
-    uint32_t* long_list[2];  // long pair indices: [0] FP32, [1] FP64
+    uint32_t* long_pend[2];            // long pairs per precision, before routing
+    uint32_t* long_list[kLongLists];  // long pair indices per list (long_list_of)
     uint32_t* long_pref;   // tile prefix of the list being run (n_long + 1)
     double* long_ring;     // per slot: kRing x 4 records, then the final sum
     uint32_t* long_prog;   // per slot: rows consumed, owner, done
@@ -138,6 +149,7 @@ struct Policy {
     float accept_min_sum;
     uint32_t watchdog_spins;
     int route_diverse;      // FP32 mode: reads with unrelated haplotypes start in FP64
+    int long_haps;          // the batch's length bound admits long pairs (routing runs)
     float cost[2][kNumClasses];  // relative cost of one wavefront-row per class
 };
 

@@ -221,21 +221,26 @@ __device__ __forceinline__ const double* long_pow<double>(const Tables& t, int g
     return t.pw64 + ((size_t)LongGeom<double>::cls * 256 + gcp) * kPowStride;
 }
 
-// Waves per SIMD the FP32 kernel is compiled for: at 3 (168 VGPRs) its row
-// loops still keep every value in registers and the long pairs run 20-24%
-// faster than at the compiler's own choice of 2; at 4 the row loops spill.
-// The FP64 kernel keeps the compiler's choice.
-template <typename R>
-constexpr int long_waves() { return sizeof(R) == 4 ? 3 : 1; }
+// Waves per SIMD the kernels are compiled for.  FP32: at 3 (168 VGPRs) the
+// row loops still keep every value in registers and the long pairs run
+// 20-24% faster than at the compiler's own choice of 2; at 4 the row loops
+// spill.  FP64: the lean kernel (no per-row gap changes, scaled form only)
+// runs at 2 (1.4-1.8x the general kernel's rate on 4-16 kbp pairs), the
+// general one keeps the compiler's choice of 1.
+template <typename R, bool GENERAL>
+constexpr int long_waves() { return sizeof(R) == 4 ? 3 : (GENERAL ? 1 : 2); }
 
-// List `which` (0: FP32 pairs, 1: FP64 pairs) in precision R.
-template <typename R>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(long_waves<R>())))
+// List long_list_of(precision of R, GENERAL) in precision R.  The lean
+// kernel (GENERAL false) runs pairs whose read has one gap byte (>= 1) and
+// the scaled row form on every row, as the packer routed them; the general
+// kernel tests each read and runs per-row gap changes and the plain form.
+template <typename R, bool GENERAL>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(long_waves<R, GENERAL>())))
 void long_kernel(Batch b, Tables t, Work w, Policy pol)
 {
     constexpr int N = LongGeom<R>::N;
     constexpr uint32_t kTile = (uint32_t)N * kWave;
-    constexpr int which = sizeof(R) == 4 ? 0 : 1;
+    constexpr int which = long_list_of(sizeof(R) == 4 ? 0 : 1, GENERAL);
     __shared__ RowRec<R> rec[kWave];
     __shared__ int rinfo[kWave];
     const int lane = (int)threadIdx.x;
@@ -317,14 +322,16 @@ void long_kernel(Batch b, Tables t, Work w, Policy pol)
             hc[n / 4] |= code << (8 * (n % 4));
         }
         // read profile: scaled row form when every gap byte is >= 1 and every
-        // insertion byte within the form's limit
+        // insertion byte within the form's limit (known for the lean kernel)
         const int g0 = b.gq[roff];
         bool sc_ok = true;
-        for (int i0 = 0; i0 < l; i0 += kWave) {
-            const int i = i0 + lane;
-            const int gc = i < l ? (int)b.gq[roff + i] : g0;
-            const int ic = i < l ? (int)b.iq[roff + i] : 0;
-            sc_ok = sc_ok && __ballot(gc == 0 || ic > kScMaxInsQ) == 0ull;
+        if constexpr (GENERAL) {
+            for (int i0 = 0; i0 < l; i0 += kWave) {
+                const int i = i0 + lane;
+                const int gc = i < l ? (int)b.gq[roff + i] : g0;
+                const int ic = i < l ? (int)b.iq[roff + i] : 0;
+                sc_ok = sc_ok && __ballot(gc == 0 || ic > kScMaxInsQ) == 0ull;
+            }
         }
         const R minit = (R)(1.0 / (double)k);
         const R* pw0 = long_pow<R>(t, g0);
@@ -356,7 +363,7 @@ void long_kernel(Batch b, Tables t, Work w, Policy pol)
                 const int info = __builtin_amdgcn_readfirstlane(rinfo[tt]);
                 const int gc = info >> 16;
                 gprev = gcur;
-                if (gc != gc_cur) {  // per-row gap continuation
+                if (GENERAL && gc != gc_cur) {  // per-row gap continuation
                     gc_cur = gc;
                     gcur = (R)t.p64[gc];
                     const R* pwi = long_pow<R>(t, gc);
@@ -528,10 +535,14 @@ void long_kernel(Batch b, Tables t, Work w, Policy pol)
                 }
             }
         };
-        if (sc_ok)
+        if constexpr (!GENERAL) {
             run_rows(std::true_type{});
-        else
-            run_rows(std::false_type{});
+        } else {
+            if (sc_ok)
+                run_rows(std::true_type{});
+            else
+                run_rows(std::false_type{});
+        }
         if (__ballot(dead) != 0ull) break;
 
         // ---- eq.4 over this tile's real columns, then accumulate along the tiles
@@ -583,27 +594,35 @@ void long_kernel(Batch b, Tables t, Work w, Policy pol)
     }
 }
 
-// Both lists in order (FP32, then FP64); a list whose grid is 0 is skipped
-// (the caller knows it is empty).
-void launch_long(hipStream_t s, const int (&grid)[2], const Batch& b, const Tables& t, const Work& w,
-                 const Policy& p)
+// Every list in order (long_list_of); a list whose grid is 0 is skipped (the
+// caller knows it is empty).  Each list's prefix kernel resets the ring
+// ownership state before its long kernel runs.
+void launch_long(hipStream_t s, const int (&grid)[kLongLists], const Batch& b, const Tables& t,
+                 const Work& w, const Policy& p)
 {
-    if (grid[0] > 0) {
-        hipLaunchKernelGGL(long_prefix_kernel, dim3(1), dim3(256), 0, s, b, w, long_slots(grid[0]),
-                           0, long_tile_cols(true));
-        hipLaunchKernelGGL(long_kernel<float>, dim3(grid[0]), dim3(kWave), 0, s, b, t, w, p);
-    }
-    if (grid[1] > 0) {
-        hipLaunchKernelGGL(long_prefix_kernel, dim3(1), dim3(256), 0, s, b, w, long_slots(grid[1]),
-                           1, long_tile_cols(false));
-        hipLaunchKernelGGL(long_kernel<double>, dim3(grid[1]), dim3(kWave), 0, s, b, t, w, p);
+    for (int q = 0; q < kLongLists; ++q) {
+        if (grid[q] <= 0) continue;
+        const bool fp32 = q < 2;
+        hipLaunchKernelGGL(long_prefix_kernel, dim3(1), dim3(256), 0, s, b, w, long_slots(grid[q]), q,
+                           long_tile_cols(fp32));
+        const dim3 g(grid[q]), blk(kWave);
+        switch (q) {
+        case 0: hipLaunchKernelGGL((long_kernel<float, false>), g, blk, 0, s, b, t, w, p); break;
+        case 1: hipLaunchKernelGGL((long_kernel<float, true>), g, blk, 0, s, b, t, w, p); break;
+        case 2: hipLaunchKernelGGL((long_kernel<double, false>), g, blk, 0, s, b, t, w, p); break;
+        default: hipLaunchKernelGGL((long_kernel<double, true>), g, blk, 0, s, b, t, w, p); break;
+        }
     }
 }
 
-const void* long_kernel_ptr(bool fp32)
+const void* long_kernel_ptr(int q)
 {
-    return fp32 ? reinterpret_cast<const void*>(&long_kernel<float>)
-                : reinterpret_cast<const void*>(&long_kernel<double>);
+    switch (q) {
+    case 0: return reinterpret_cast<const void*>(&long_kernel<float, false>);
+    case 1: return reinterpret_cast<const void*>(&long_kernel<float, true>);
+    case 2: return reinterpret_cast<const void*>(&long_kernel<double, false>);
+    default: return reinterpret_cast<const void*>(&long_kernel<double, true>);
+    }
 }
 
 size_t long_ring_slot_bytes() { return kRingSlotBytes; }

@@ -9,7 +9,8 @@
 // priors and the read base are uniform across the wavefront.  In FP32 mode a
 // run whose haplotypes are mutually unrelated starts in FP64 (most of its
 // pairs would be rejected by the FP32 threshold).  Haplotypes
-// longer than 64 * kMaxN columns go to the long-pair list.
+// longer than 64 * kMaxN columns go to one of the long-pair lists (by
+// precision, and by whether the read allows the lean long kernel).
 //
 // Five kernels, no contended global atomics: count (per-block segment pack
 // counts from LDS atomics, one greedy pass that sizes all classes at once),
@@ -126,6 +127,83 @@ __device__ __forceinline__ uint32_t ceil_div_small(uint32_t k, uint32_t n, float
     return s;
 }
 
+// OR of word(w) over the 4-byte words of the 16-byte-aligned blocks of
+// v[0, l) and of byte(x) over the bytes before the first and after the last
+// such block.  The kLanes lanes of a group share the scan: lane `sub` takes
+// every kLanes-th block (two loads in flight) and every kLanes-th loose byte.
+template <int kLanes, typename W, typename B>
+__device__ __forceinline__ uint32_t scan_bytes(const uint8_t* v, uint32_t l, int sub, W word, B byte)
+{
+    const uintptr_t s0 = (uintptr_t)v, s1 = s0 + l;
+    const uintptr_t a0 = (s0 + 15u) & ~(uintptr_t)15u, a1 = s1 & ~(uintptr_t)15u;
+    uint32_t bad = 0u;
+    if (a0 >= a1) {
+        for (uint32_t i = (uint32_t)sub; i < l; i += kLanes) bad |= byte(v[i]);
+        return bad;
+    }
+    for (uint32_t i = (uint32_t)sub; i < (uint32_t)(a0 - s0); i += kLanes) bad |= byte(v[i]);
+    const uint8_t* t = reinterpret_cast<const uint8_t*>(a1);
+    for (uint32_t i = (uint32_t)sub; i < (uint32_t)(s1 - a1); i += kLanes) bad |= byte(t[i]);
+    const uint4* V = reinterpret_cast<const uint4*>(a0);
+    const uint32_t nb = (uint32_t)((a1 - a0) / 16u);
+    for (uint32_t q = (uint32_t)sub; q < nb; q += 2 * kLanes) {
+        const uint32_t q2 = q + kLanes;
+        const uint4 x = V[q];
+        const uint4 y = q2 < nb ? V[q2] : x;
+        bad |= word(x.x) | word(x.y) | word(x.z) | word(x.w);
+        bad |= word(y.x) | word(y.y) | word(y.z) | word(y.w);
+    }
+    return bad;
+}
+
+// Whether a read needs the general long kernel: a gap byte of 0, more than
+// one gap byte, or an insertion byte above kScMaxInsQ on some row.  Words of
+// gap bytes are compared with the first byte replicated; a word of insertion
+// bytes has one above kScMaxInsQ when its top bit is set or its low seven
+// bits plus 127 - kScMaxInsQ carry into it.
+template <int kLanes>
+__device__ __forceinline__ int read_needs_general(const Batch& b, uint64_t roff, uint32_t l, int sub)
+{
+    const uint32_t g0 = b.gq[roff];
+    if (g0 == 0u) return 1;
+    const uint32_t g4 = g0 * 0x01010101u;
+    constexpr uint32_t kAdd = (127u - (uint32_t)kScMaxInsQ) * 0x01010101u;
+    const uint32_t bad_g = scan_bytes<kLanes>(
+        b.gq + roff, l, sub, [g4](uint32_t w) { return w ^ g4; },
+        [g0](uint8_t x) { return (uint32_t)(x != g0); });
+    const uint32_t bad_i = scan_bytes<kLanes>(
+        b.iq + roff, l, sub, [](uint32_t w) { return (((w & 0x7f7f7f7fu) + kAdd) | w) & 0x80808080u; },
+        [](uint8_t x) { return (uint32_t)(x > kScMaxInsQ); });
+    return (bad_g | bad_i) != 0u;
+}
+
+// Routing of long pairs: one workgroup per pair queued by the count kernel
+// scans the pair's read and appends the pair to the lean or the general long
+// list of its precision.  A read is scanned once per long pair: at most its
+// length in bytes against at least kShortMaxCols cells per row of the pair.
+constexpr int kRouteBlock = 256;
+constexpr int kRouteGrid = 1024;
+
+__global__ __launch_bounds__(kRouteBlock) void long_route_kernel(Batch b, Work w)
+{
+    const int t = (int)threadIdx.x;
+    for (int prec = 0; prec < 2; ++prec) {
+        const uint32_t n = w.ctr->n_pend[prec];
+        for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {  // workgroup-uniform
+            const uint32_t pair = w.long_pend[prec][i];
+            const uint32_t r = b.pairs[2 * (uint64_t)pair];
+            const uint64_t roff = b.read_off[r];
+            const uint32_t l = (uint32_t)(b.read_off[r + 1] - roff);
+            const int slow = __syncthreads_or(read_needs_general<kRouteBlock>(b, roff, l, t));
+            if (t == 0) {
+                const int q = long_list_of(prec, slow != 0);
+                const uint32_t idx = atomicAdd(&w.ctr->n_long[q], 1u);
+                w.long_list[q][idx] = pair;
+            }
+        }
+    }
+}
+
 // Pass 1: precision and class per run, pack counts per (segment, block);
 // long pairs to the long list.  Each wavefront takes the runs that start in
 // its 64 pairs, nine at a time: the 7 lanes 7g .. 7g + 6 size run g, each in
@@ -140,6 +218,7 @@ constexpr int kRunLanes = 7;                           // lanes per run
 constexpr int kRunClasses = kNumClasses / kRunLanes;   // classes per lane
 constexpr int kRunsPerWave = kWave / kRunLanes;        // runs sized at once
 static_assert(kRunClasses * kRunLanes == kNumClasses, "classes split evenly over a run's lanes");
+
 
 __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w, Policy pol)
 {
@@ -182,13 +261,11 @@ __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w,
             fits[i] = true;
         }
         uint32_t nshort = 0;
+        int mylong = 0;  // this lane met a long pair of the run
         for (uint64_t base = p; base < e; base += kRunLanes) {
             const uint64_t mine_q = base + (uint64_t)sub;
             const uint32_t mine_k = mine_q < e ? hap_len(b, b.pairs[2 * mine_q + 1]) : 0u;
-            if (mine_k > kShortMaxCols) {  // this lane's pair is long
-                const uint32_t idx = atomicAdd(&w.ctr->n_long[lprec], 1u);
-                w.long_list[lprec][idx] = (uint32_t)mine_q;
-            }
+            mylong |= mine_k > kShortMaxCols ? 1 : 0;
             const int m = (int)min<uint64_t>((uint64_t)kRunLanes, e - base);
             for (int j = 0; j < m; ++j) {
                 const uint32_t k = (uint32_t)__shfl((int)mine_k, lead + j, kWave);
@@ -207,6 +284,22 @@ __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w,
                     const uint32_t sl = ceil_div_small(k, N, rcp[i]);
                     if (sl > (uint32_t)kWave) fits[i] = false;
                     else gr[i].add(sl, pol.one_pair_per_wave);
+                }
+            }
+        }
+        // long pairs of the run wait for routing (lean or general long list).
+        // A haplotype beyond the batch's stated length bound (no routing
+        // launched) is an error; its pair still goes to the FP64 general
+        // list, which every call runs, so that its output is written.
+        const int src = active ? lead : lane;
+        if (active && mylong) {
+            if (!pol.long_haps) w.ctr->bound_err = 1u;
+            for (uint64_t base = p; base < e; base += kRunLanes) {
+                const uint64_t mine_q = base + (uint64_t)sub;
+                if (mine_q < e && hap_len(b, b.pairs[2 * mine_q + 1]) > kShortMaxCols) {
+                    uint32_t* cnt = pol.long_haps ? &w.ctr->n_pend[lprec] : &w.ctr->n_long[long_list_of(1, true)];
+                    uint32_t* list = pol.long_haps ? w.long_pend[lprec] : w.long_list[long_list_of(1, true)];
+                    list[atomicAdd(cnt, 1u)] = (uint32_t)mine_q;
                 }
             }
         }
@@ -229,7 +322,6 @@ __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w,
                 ++seen;
             }
         }
-        const int src = active ? lead : lane;
         uint64_t ref[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) ref[q] = shfl64(km[q], src);
@@ -468,6 +560,9 @@ __global__ __launch_bounds__(kPackBlock) void pack_emit_kernel(Batch b, Work w, 
 void launch_pack(hipStream_t s, const Batch& b, const Work& w, const Policy& pol)
 {
     hipLaunchKernelGGL(pack_count_kernel, dim3(w.n_pack_blocks), dim3(kPackBlock), 0, s, b, w, pol);
+    if (pol.long_haps)
+        hipLaunchKernelGGL(long_route_kernel, dim3((uint32_t)std::min<uint64_t>(b.n_pairs, kRouteGrid)),
+                           dim3(kRouteBlock), 0, s, b, w);
     hipLaunchKernelGGL(pack_chunk_sum_kernel, dim3(w.n_scan_chunks, kSeg), dim3(256), 0, s, w);
     hipLaunchKernelGGL(pack_scan_kernel, dim3(1), dim3(1024), 0, s, w);
     hipLaunchKernelGGL(pack_block_offset_kernel, dim3(w.n_scan_chunks, kSeg), dim3(256), 0, s, w);

@@ -374,8 +374,9 @@ void short_kernel(Batch b, Tables t, Work w, Policy pol)
                 // FP64 scaled sums this small would have lost bits to
                 // underflow: hand the pair to the rescaling long-pair kernel.
                 if (!(S >= 1e-290)) {
-                    const uint32_t idx = atomicAdd(&ctr->n_long[1], 1u);
-                    w.long_list[1][idx] = pair;
+                    constexpr int q = long_list_of(1, true);
+                    const uint32_t idx = atomicAdd(&ctr->n_long[q], 1u);
+                    w.long_list[q][idx] = pair;
                 } else {
                     b.out[pair] = log10_scaled(S, ScaleOf<R>::exp);
                     if (b.flags) b.flags[pair] = rerun_item ? (0x02 | 0x10) : 0x10;

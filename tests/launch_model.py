@@ -53,6 +53,7 @@ class Policy:
         self.fp32_max_rows = fp32_max_rows
         self.long_fp32_max_rows = long_fp32_max_rows
         self.route_diverse = route_diverse
+        self.long_haps = True  # the batch's haplotype bound admits long pairs
         self.cost = cost if cost is not None else [[class_n(c) + 3.0 for c in range(NUM_CLASSES)]
                                                    for _ in range(2)]
 
@@ -65,6 +66,7 @@ class Policy:
             k = max(1, min(max_hap_len, SHORT_MAX_COLS))
             n = max(class_n(0), (k + WAVE - 1) // WAVE)
             p.force_class = min(n, MAX_N) - 4
+        p.long_haps = max_hap_len > SHORT_MAX_COLS
         return p
 
 
@@ -97,7 +99,11 @@ class LaunchModel:
         self.ro, self.ho = ro, ho
         cap = max(self.n, 1)
         self.cap = cap  # every per-pair array of the workspace holds n_pairs entries
-        self.long_list = [[], []]
+        # long lists q = 2 * precision + general (general: the read has
+        # several gap bytes, a gap byte 0 or an insertion byte over 65)
+        self.long_list = [[], [], [], []]
+        self.long_pend = [[], []]  # per precision, before routing
+        self.bound_error = False   # a long pair in a batch whose bound says none
         self.out_writes = np.zeros(self.n, np.int64)
         self.flags = np.zeros(self.n, np.int64)
 
@@ -131,8 +137,13 @@ class LaunchModel:
             for q in range(p, e):
                 k = self.k_of(q)
                 if k > SHORT_MAX_COLS:
-                    self.long_list[lprec].append(q)
-                    need(len(self.long_list[lprec]) <= self.cap, "long list overflow")
+                    if pol.long_haps:
+                        self.long_pend[lprec].append(q)
+                        need(len(self.long_pend[lprec]) <= self.cap, "pending long list overflow")
+                    else:
+                        self.bound_error = True
+                        self.long_list[3].append(q)
+                        need(len(self.long_list[3]) <= self.cap, "long list overflow")
                     used = [WAVE] * NUM_CLASSES
                     np_ = [0] * NUM_CLASSES
                     continue
@@ -253,6 +264,17 @@ class LaunchModel:
             need(0 <= f and f + cnt <= WAVE, "segment lanes outside the wavefront")
         return segs
 
+    def route(self):
+        """The routing kernel: each pending long pair goes to the lean list
+        of its precision when its read has one gap byte (>= 1) and insertion
+        bytes the scaled row form allows, else to the general one."""
+        for prec in (0, 1):
+            for q in self.long_pend[prec]:
+                varying, sc_ok = self._read_profile(q)
+                lq = 2 * prec + (0 if (sc_ok and not varying) else 1)
+                self.long_list[lq].append(q)
+                need(len(self.long_list[lq]) <= self.cap, "long list overflow")
+
     def _read_profile(self, start):
         r = self.pl[start, 0]
         a, b = self.ro[r], self.ro[r + 1]
@@ -267,6 +289,8 @@ class LaunchModel:
         accept32(pair) / ok64(pair): whether the FP32 sum passes the threshold
         and whether the FP64 sum is above the hand-off bound."""
         self.pack()
+        if self.pol.long_haps:
+            self.route()
         defer = [[] for _ in range(NUM_CLASSES)]
         items = [[] for _ in range(NUM_CLASSES)]
         if self.pol.precision == 0:
@@ -294,13 +318,13 @@ class LaunchModel:
                     if ok64(pair):
                         self._write(pair, 0x12 if m is not None else 0x10)
                     else:
-                        self.long_list[1].append(pair)
-                        need(len(self.long_list[1]) <= self.cap, "FP64 long list overflow")
-        for which in (0, 1):
+                        self.long_list[3].append(pair)
+                        need(len(self.long_list[3]) <= self.cap, "FP64 long list overflow")
+        for which in range(4):
             if self.long_list[which]:
-                self.long_protocol(which, grids[which])
+                self.long_protocol(which, grids[which // 2])
                 for pair in self.long_list[which]:
-                    self._write(pair, 0x0c | (0x01 if which == 0 else 0x10))
+                    self._write(pair, 0x0c | (0x01 if which < 2 else 0x10))
         for q in range(self.n):
             need(self.out_writes[q] == 1, "pair %d written %d times" % (q, self.out_writes[q]))
         return self.flags

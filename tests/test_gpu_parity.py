@@ -375,6 +375,31 @@ def test_long_pairs_band_crosses_tiles_low_gap_penalty(ctx32, ctx64):
         say("band-crossing long pairs: flags %s, errors %s" % (list(fl), d))
 
 
+def test_long_pairs_lean_and_general_kernels(ctx32, ctx64):
+    """Long pairs of both routes in one batch and both precisions: reads with
+    one gap byte and insertion bytes of at most 65 run in the lean long
+    kernel, reads with per-row gap bytes, an insertion byte above 65 or a gap
+    byte of 0 in the general one (per-row gap changes, plain row form)."""
+    rng = np.random.default_rng(44)
+    pairs = []
+    for l, iq, gq in ((1500, 30, 10),                                    # lean
+                      (1800, 45, 10),                                    # lean
+                      (1600, 30, rng.integers(3, 30, 1600)),              # per-row gaps
+                      (1400, np.where(np.arange(1400) % 97 == 0, 70, 30), 10),  # ins > 65
+                      (1700, 30, np.where(np.arange(1700) == 800, 0, 10))):    # a gap byte 0
+        hap = rnd(rng, l + 400)
+        read = bytearray(hap[200:200 + l])
+        for j in rng.integers(0, l, l // 40):
+            read[j] = ord("ACGT"[int(rng.integers(0, 4))])
+        pairs.append((bytes(read), hap, rng.integers(10, 41, l), iq, 30, gq))
+    b = make_batch(pairs)
+    for ctx in (ctx32, ctx64):
+        out, fl = phmm.phmm_forward_batch(ctx, b)
+        assert np.all(fl & phmm.PHMM_FLAG_LONG)
+        want, d = check(b, out, fl)
+        say("lean/general long pairs: flags %s, errors %s" % (list(fl), d))
+
+
 def test_fp64_underflow_goes_to_rescaled_kernel(ctx64):
     """A short pair whose FP64 scaled sum underflows (log10 L < -597) is
     recomputed by the rescaling kernel."""
@@ -487,6 +512,34 @@ def _async_pass(ctx, b):
     s.synchronize()
     phmm.phmm_device_status(ctx, ws)
     return out.cpu().numpy(), fl.cpu().numpy(), phmm.phmm_last_counts(ctx, ws)
+
+
+def test_async_long_pair_beyond_stated_bound(ctx32):
+    """A 1600-base haplotype in a device batch whose max_hap_len says 1536
+    (every haplotype within the short kernels' reach): no routing of long
+    pairs is launched, the pair is computed by the FP64 general long kernel,
+    which every call runs, and phmm_device_status reports PHMM_ERANGE."""
+    import torch
+    rng = np.random.default_rng(45)
+    pairs = []
+    for k in (300, 1600, 700):
+        hap = rnd(rng, k)
+        pairs.append((hap[100:190], hap, rng.integers(10, 41, 90), 45, 45, 10))
+    b = make_batch(pairs)
+    db = phmm.DeviceBatch(b)
+    db.max_hap_len = 1536
+    ws = torch.empty(phmm.phmm_workspace_bytes(ctx32, 3, db.max_read_len, db.max_hap_len),
+                     dtype=torch.uint8, device="cuda:0")
+    out = torch.empty(3, dtype=torch.float64, device="cuda:0")
+    fl = torch.empty(3, dtype=torch.uint8, device="cuda:0")
+    phmm.phmm_forward_batch_async(ctx32, db, out, fl, ws, None)
+    with pytest.raises(phmm.PhmmError) as e:
+        phmm.phmm_device_status(ctx32, ws)
+    assert e.value.code == phmm.PHMM_ERANGE
+    out, fl = out.cpu().numpy(), fl.cpu().numpy()
+    check(b, out, fl)
+    assert fl[1] & phmm.PHMM_FLAG_LONG and fl[1] & phmm.PHMM_FLAG_FP64
+    say("long pair beyond the stated bound: flags %s" % list(fl))
 
 
 def test_async_matches_sync(ctx32):

@@ -67,6 +67,8 @@ def test_edge_batch_protocol():
         # the 1537-column pair is the only long pair from the packer
         long_from_packer = [q for q in range(m.n) if m.k_of(q) > 1536]
         assert long_from_packer == [9]
+        # its read has one gap byte and insertion bytes of 45: the lean list
+        assert 9 in m.long_list[0] or 9 in m.long_list[2]
     assert n_runs == 6
 
 
@@ -79,7 +81,7 @@ def test_edge_batch_l_zero_path():
     assert want[10] == -np.inf
     m = LaunchModel(b, Policy(precision=0).for_batch(len(b["pair_list"]), 1537))
     flags = m.run(lambda q: want[q] >= THRESH32, lambda q: want[q] >= THRESH64)
-    assert 10 in m.long_list[1] and flags[10] == 0x1c
+    assert 10 in m.long_list[3] and flags[10] == 0x1c
     assert flags[9] == 0x0d  # FP32 long pair
 
 
@@ -112,6 +114,22 @@ def long_batch(lengths, read_len, seed=3):
         h = bytes(rng.choice(np.frombuffer(b"ACGT", np.uint8), k))
         pairs.append((h[:read_len], h, 30, 45, 45, 10))
     return make_batch(pairs)
+
+
+def test_long_pair_beyond_stated_bound():
+    """A long haplotype in a batch whose length bound says every haplotype
+    fits the short kernels: no routing runs, the pair goes to the FP64
+    general list (launched in every call) and the call reports the bound
+    error; its output is still written once."""
+    b = long_batch([100, 1600, 200], read_len=90)
+    for prec in (0, 1):
+        m = LaunchModel(b, Policy(precision=prec).for_batch(3, 1536))
+        m.run(lambda q: True, lambda q: True)
+        assert m.bound_error and m.long_list[3] == [1]
+        assert not any(m.long_list[:3])
+        m = LaunchModel(b, Policy(precision=prec).for_batch(3, 1600))
+        m.run(lambda q: True, lambda q: True)
+        assert not m.bound_error and m.long_list[2 * prec] == [1]
 
 
 def test_long_pipeline_slot_reuse():
