@@ -183,6 +183,20 @@ __global__ void long_prefix_kernel(Batch b, Work w, uint32_t nslot, int which, u
     for (uint32_t s = (uint32_t)t; s < 3 * nslot; s += 256) w.long_prog[s] = 0u;
 }
 
+// Wavefronts of a grid of g that take tiles.  With fewer tiles than
+// wavefronts, the first tiles.  Tiles are claimed in arrival order, and the
+// first wavefronts to arrive can crowd a few SIMDs (up to 4 tiles on one
+// while others hold none); the workgroups with the lowest indices are
+// spread over the XCDs and CUs by the dispatcher, so only they take tiles
+// and the others leave at once (16 pairs of 64 tiles on a grid of 4096:
+// 1368 -> 1600 GCUPS).  With more tiles than wavefronts every wavefront
+// stays: cutting the grid to make rounds of equal size helps only when all
+// tiles take equally long, and halves the rate of mixed lengths.
+__host__ __device__ uint32_t long_active_waves(uint32_t tiles, uint32_t g)
+{
+    return tiles > 0u && tiles < g ? tiles : g;
+}
+
 template <typename R>
 __device__ __forceinline__ R rd_lane(R v, int lane);
 template <>
@@ -228,7 +242,7 @@ __device__ __forceinline__ const double* long_pow<double>(const Tables& t, int g
 // runs at 2 (1.4-1.8x the general kernel's rate on 4-16 kbp pairs), the
 // general one keeps the compiler's choice of 1.
 template <typename R, bool GENERAL>
-constexpr int long_waves() { return sizeof(R) == 4 ? 3 : (GENERAL ? 1 : 2); }
+constexpr int long_waves() { return sizeof(R) == 4 ? (GENERAL ? 3 : 4) : (GENERAL ? 1 : 2); }
 
 // List long_list_of(precision of R, GENERAL) in precision R.  The lean
 // kernel (GENERAL false) runs pairs whose read has one gap byte (>= 1) and
@@ -243,6 +257,16 @@ void long_kernel(Batch b, Tables t, Work w, Policy pol)
     constexpr int which = long_list_of(sizeof(R) == 4 ? 0 : 1, GENERAL);
     __shared__ RowRec<R> rec[kWave];
     __shared__ int rinfo[kWave];
+    // producer records of the current window, row i0 + q at lane or entry q,
+    // in the producer's scale: magnitudes, exponent, and the exponent of the
+    // largest field (kNoRec when there is none).  They are read once per
+    // kRescaleRows rows: FP32 keeps them in LDS (each lane writes and reads
+    // its own entry, no barrier), which frees the registers of a fourth wave
+    // per SIMD; FP64 keeps them in registers (in LDS its lean kernel ran
+    // 20-25% slower at 16 kbp).
+    constexpr bool kWinLds = sizeof(R) == 4;
+    __shared__ R winM[kWinLds ? kWave : 1], winI[kWinLds ? kWave : 1], winP[kWinLds ? kWave : 1];
+    __shared__ int winE[kWinLds ? kWave : 1], winTop[kWinLds ? kWave : 1];
     const int lane = (int)threadIdx.x;
     const uint32_t nslot = long_slots((int)gridDim.x);
     const SlotState ss = slot_state(w, nslot);
@@ -250,6 +274,7 @@ void long_kernel(Batch b, Tables t, Work w, Policy pol)
     const uint32_t n_long = w.ctr->n_long[which];
     const uint32_t* list = w.long_list[which];
     const uint32_t spin_limit = pol.watchdog_spins;
+    if (blockIdx.x >= long_active_waves(total, gridDim.x)) return;
 
     for (;;) {
         uint32_t it = 0;
@@ -349,10 +374,7 @@ void long_kernel(Batch b, Tables t, Work w, Policy pol)
 
         auto run_rows = [&](auto sc_tag) {
             constexpr bool SC = decltype(sc_tag)::value;
-            // producer records of the current window, lane q holding row
-            // i0 + q in the producer's scale (magnitudes, exponent, and the
-            // exponent of the largest field: kNoRec when there is none)
-            R rM = (R)0, rI = (R)0, rP = (R)0;
+            R rM = (R)0, rI = (R)0, rP = (R)0;  // window records in registers (FP64)
             int rE = 0, rTop = kNoRec;
             // the current group's records brought to this tile's scale
             R wM = (R)0, wI = (R)0, wP = (R)0;
@@ -447,7 +469,9 @@ void long_kernel(Batch b, Tables t, Work w, Policy pol)
             // power-of-two scalings over the full exponent range (ldexp), so
             // values far below the new scale flush to 0 and nothing overflows.
             auto take_records = [&](int tt, int ng) {
-                const int rel = lane >= tt && lane < tt + ng && rTop != kNoRec ? rTop - E : kNoRec;
+                int top_e = rTop;
+                if constexpr (kWinLds) top_e = winTop[lane_here()];
+                const int rel = lane >= tt && lane < tt + ng && top_e != kNoRec ? top_e - E : kNoRec;
                 const int top = wave_max_int(rel - kNoRec + 1) - 1 + kNoRec;
                 if (top > LongGeom<R>::rebase_bits) {
 #pragma unroll
@@ -460,10 +484,18 @@ void long_kernel(Batch b, Tables t, Work w, Policy pol)
                     C = scale2(C, -top);
                     E += top;
                 }
-                const int sh = max(min(rE - E, 4000), -4000);
-                wM = scale2(rM, sh);
-                wI = scale2(rI, sh);
-                wP = scale2(rP, sh);
+                if constexpr (kWinLds) {
+                    const int me = lane_here();
+                    const int sh = max(min(winE[me] - E, 4000), -4000);
+                    wM = scale2(winM[me], sh);
+                    wI = scale2(winI[me], sh);
+                    wP = scale2(winP[me], sh);
+                } else {
+                    const int sh = max(min(rE - E, 4000), -4000);
+                    wM = scale2(rM, sh);
+                    wI = scale2(rI, sh);
+                    wP = scale2(rP, sh);
+                }
             };
             for (int i0 = 0; i0 < l && !dead; i0 += kWave) {
                 __syncthreads();
@@ -509,6 +541,14 @@ void long_kernel(Batch b, Tables t, Work w, Policy pol)
                     rP = magnitude(bP);
                     const R mrec = maxR(rM, maxR(rI, rP));
                     rTop = lane < nrows && mrec > (R)0 ? rE + exponent_of(mrec) : kNoRec;
+                    if constexpr (kWinLds) {
+                        const int me = lane_here();
+                        winM[me] = rM;
+                        winI[me] = rI;
+                        winP[me] = rP;
+                        winE[me] = rE;
+                        winTop[me] = rTop;
+                    }
                 }
                 int tt = 0;
                 // groups of kRescaleRows rows: ping-pong in pairs, rescale at the end

@@ -44,6 +44,12 @@ def need(cond: bool, what: str):
         raise ModelError(what)
 
 
+def long_active_waves(tiles: int, g: int) -> int:
+    """Wavefronts of a long-kernel grid of g that take tiles: the first
+    `tiles` when there are fewer tiles than wavefronts, else all."""
+    return tiles if 0 < tiles < g else g
+
+
 class Policy:
     def __init__(self, precision=0, force_class=-1, one_pair_per_wave=False, fp32_max_rows=2048,
                  long_fp32_max_rows=131072, route_diverse=True, cost=None):
@@ -355,6 +361,8 @@ class LaunchModel:
         total = int(pref[-1])
         grid = grid or 1024
         nslot = 2 * grid
+        active = long_active_waves(total, grid)
+        need(active <= grid, "active wavefronts within the grid")
         done = [0] * nslot
         owner = [0] * nslot
         prog = [0] * nslot
@@ -366,7 +374,7 @@ class LaunchModel:
             pass
 
         waves = []
-        for _ in range(grid):
+        for _ in range(active):
             w = Wave()
             w.state = "claim"
             waves.append(w)

@@ -12,7 +12,7 @@ import pytest
 import oracle
 import synth
 from edge_batch import edge_pairs, make_batch
-from launch_model import (LONG_TILE, RING, LaunchModel, ModelError, Policy)
+from launch_model import (LONG_TILE, RING, LaunchModel, ModelError, Policy, long_active_waves)
 
 THRESH32 = -28.0 - 120 * math.log10(2.0)    # log10 L at an FP32 scaled sum of 1e-28
 THRESH64 = -290.0 - 1020 * math.log10(2.0)  # FP64 scaled sums under 1e-290 go long
@@ -140,6 +140,18 @@ def test_long_pipeline_slot_reuse():
     for grid in (2, 3, 5, 64):
         m = LaunchModel(b, Policy(precision=1))
         m.run(lambda q: True, lambda q: True, grids=(grid, grid))
+
+
+def test_long_grid_cut_to_tiles():
+    """With fewer tiles than wavefronts only the first `tiles` wavefronts of
+    the long kernel's grid take tiles (every tile still resident at once, so
+    the pipeline drains); with more, every wavefront stays."""
+    assert long_active_waves(1024, 4096) == 1024
+    assert long_active_waves(6144, 4096) == 4096
+    assert long_active_waves(0, 4096) == 4096
+    b = long_batch([LONG_TILE * 40] * 3, read_len=RING * 3 + 5)  # 120 tiles on 300
+    m = LaunchModel(b, Policy(precision=1))
+    m.run(lambda q: True, lambda q: True, grids=(300, 300))
 
 
 def test_long_pipeline_needs_resident_consumers():
