@@ -452,11 +452,14 @@ int phmm_copy_calib(const void* src, void* dst, uint64_t bytes, void* stream);
  * submission with PHMM_ENOMEM.
  *
  * Long regions (a haplotype longer than 64 x 24 columns or a read longer than
- * 2048 bases) queue apart and run on the long_lanes last lanes when
- * long_lanes > 0; with short_cu_percent in 1..99 the short lanes' streams are
- * restricted to that share of the compute units and the long lanes' to the
- * rest (CU masks; if the device refuses a mask the lanes run unrestricted and
- * phmm_server_stats reports it).
+ * long_read_min bases) queue apart and run on the long_lanes last lanes when
+ * long_lanes > 0.  Each lane's stream is created with a CU mask, which gives
+ * it a hardware queue of its own (plain streams share the process's few
+ * hardware queues, and a short lane sharing one with a long lane would wait
+ * behind its long kernels): the mask holds every compute unit, or with
+ * short_cu_percent in 1..99 that share of them for the short lanes and the
+ * rest for the long lanes.  If the device refuses a mask the lanes get plain
+ * streams and phmm_server_stats reports it.
  */
 typedef struct phmm_server phmm_server;
 
@@ -496,7 +499,8 @@ typedef struct phmm_server_counters {
     uint64_t waiting_short, waiting_long;  /* regions queued now                        */
     double lane_busy_s;              /* summed over lanes: batch start to completion     */
     double span_s;                   /* first submission to last completion              */
-    int cu_mask_status;              /* 0 no masks asked, 1 applied, < 0 refused         */
+    int cu_mask_status;              /* 1 CU-masked lane streams, < 0 refused (HIP error,
+                                        negated; plain streams instead)                  */
 } phmm_server_counters;
 
 void phmm_server_default_options(phmm_server_options* opt);

@@ -178,3 +178,25 @@ def test_cu_masked_lanes(stream_regions):
         for r, (b, fb, _) in zip(regs, got):
             a, fa = phmm.phmm_forward_batch(ctx, r)
             compare(a, fa, b, fb, near=True)
+
+
+def test_lanes_have_their_own_queues(stream_regions):
+    """With default options every lane's stream is CU-masked (all compute
+    units), which gives it a hardware queue of its own: streams the process
+    created before the server cannot put a short lane behind a long one."""
+    import torch
+    others = [torch.cuda.Stream() for _ in range(4)]
+    for s in others:
+        with torch.cuda.stream(s):
+            torch.ones(16, device="cuda:0").sum()
+    torch.cuda.synchronize()
+    regs = stream_regions[:20]
+    with phmm.Server(hbm_budget_bytes=3 << 30) as srv:
+        ts = [srv.submit(r) for r in regs]
+        got = [srv.wait(t) for t in ts]
+        st = srv.stats()
+    assert st["cu_mask_status"] == 1
+    with phmm.Context() as ctx:
+        for r, (b, fb, _) in zip(regs, got):
+            a, fa = phmm.phmm_forward_batch(ctx, r)
+            compare(a, fa, b, fb, near=True)
