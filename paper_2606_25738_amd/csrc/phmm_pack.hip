@@ -231,7 +231,13 @@ __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w,
     const int lane = t & (kWave - 1);
     const uint64_t p0 = (uint64_t)blockIdx.x * blockDim.x + (uint64_t)(t - lane);
     const uint64_t mine = p0 + (uint64_t)lane;
-    uint64_t starts = __ballot(mine < b.n_pairs && run_start(b, mine));
+    // read of each of the wavefront's pairs, and the run starts among them
+    const uint32_t my_r = mine < b.n_pairs ? b.pairs[2 * mine] : 0u;
+    const uint32_t left_r = (uint32_t)__shfl((int)my_r, lane > 0 ? lane - 1 : 0, kWave);
+    const bool my_start = mine < b.n_pairs &&
+                          (mine % kChunk == 0 || my_r != (lane > 0 ? left_r : b.pairs[2 * mine - 2]));
+    uint64_t starts = __ballot(my_start);
+    const uint64_t all_starts = starts;
     const int g = lane / kRunLanes, sub = lane - g * kRunLanes;  // g = 9: idle lane
     const int lead = g * kRunLanes;
     float rcp[kRunClasses];
@@ -244,12 +250,22 @@ __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w,
         const bool active = g < kRunsPerWave && rest != 0ull;
         const uint64_t p = active ? p0 + (uint64_t)(__ffsll((unsigned long long)rest) - 1) : 0ull;
         for (int j = 0; j < kRunsPerWave && starts; ++j) starts &= starts - 1;
-        const uint64_t e = active ? run_end(b, p) : p;
-        uint32_t l = 0;
+        // the run ends at the next start in the wavefront, else it continues
+        // past the wavefront's last pair
+        const int pl = active ? (int)(p - p0) : 0;
+        const uint32_t r = (uint32_t)__shfl((int)my_r, pl, kWave);
+        uint64_t e = p;
         if (active) {
-            const uint32_t r = b.pairs[2 * p];
-            l = (uint32_t)(b.read_off[r + 1] - b.read_off[r]);
+            const uint64_t above = pl < kWave - 1 ? all_starts & (~0ull << (pl + 1)) : 0ull;
+            if (above) {
+                e = p0 + (uint64_t)(__ffsll((unsigned long long)above) - 1);
+            } else {
+                e = min(p0 + (uint64_t)kWave, b.n_pairs);
+                while (e < b.n_pairs && b.pairs[2 * e] == r && (e % kChunk) != 0) ++e;
+            }
         }
+        uint32_t l = 0;
+        if (active) l = (uint32_t)(b.read_off[r + 1] - b.read_off[r]);
         int prec = (pol.precision == 1 || l > pol.fp32_max_rows) ? 1 : 0;
         const int lprec = (pol.precision == 1 || l > pol.long_fp32_max_rows) ? 1 : 0;
         // this lane's classes sub * kRunClasses + i over the run
@@ -262,9 +278,15 @@ __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w,
         }
         uint32_t nshort = 0;
         int mylong = 0;  // this lane met a long pair of the run
+        uint32_t first_h = 0u, first_k = 0u;  // haplotype and length of pair p + sub
         for (uint64_t base = p; base < e; base += kRunLanes) {
             const uint64_t mine_q = base + (uint64_t)sub;
-            const uint32_t mine_k = mine_q < e ? hap_len(b, b.pairs[2 * mine_q + 1]) : 0u;
+            const uint32_t mine_h = mine_q < e ? b.pairs[2 * mine_q + 1] : 0u;
+            const uint32_t mine_k = mine_q < e ? hap_len(b, mine_h) : 0u;
+            if (base == p) {
+                first_h = mine_h;
+                first_k = mine_k;
+            }
             mylong |= mine_k > kShortMaxCols ? 1 : 0;
             const int m = (int)min<uint64_t>((uint64_t)kRunLanes, e - base);
             for (int j = 0; j < m; ++j) {
@@ -304,11 +326,21 @@ __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(Batch b, Work w,
             }
         }
         // unrelated haplotypes: lanes sub = 0..3 take the run's sub-th short
-        // haplotype of at least 8 bases
+        // haplotype of at least 8 bases: pair p + sub when the pairs p ..
+        // p + sub all have one (their lengths are at hand), else by a walk
         const bool check = active && prec == 0 && pol.route_diverse && e - p >= 2;
+        const int qual = (p + (uint64_t)sub < e && first_k >= 8u && first_k <= kShortMaxCols) ? 1 : 0;
+        int prefix = 1;
+        for (int j = 0; j < 4; ++j) {
+            const int qj = __shfl(qual, src + j, kWave);
+            if (j <= sub) prefix &= qj;
+        }
         uint64_t km[4] = {0ull, 0ull, 0ull, 0ull};
         bool have = false;
-        if (check && sub < 4) {
+        if (check && sub < 4 && prefix) {
+            kmer_set(b, first_h, km);
+            have = true;
+        } else if (check && sub < 4) {
             int seen = 0;
             for (uint64_t q = p; q < e; ++q) {
                 const uint32_t h = b.pairs[2 * q + 1];
