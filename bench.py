@@ -305,8 +305,8 @@ def summarize_long_counters(pmc_csv, sweep_json, out_path, commands):
     JSON line gives each length's cells).  For each length and precision the
     counters of the timed passes' long-kernel dispatches are averaged per
     pass; VALU per CU-clock = SQ_INSTS_VALU / SQ_BUSY_CU_CYCLES, resident waves
-    per SIMD = SQ_WAVE_CYCLES / SQ_BUSY_CU_CYCLES (calibrated on the FP64 long
-    kernel, which holds exactly one wave per SIMD and reads 1.00)."""
+    per SIMD = SQ_WAVE_CYCLES / SQ_BUSY_CU_CYCLES (calibrated on the general
+    FP64 long kernel, which holds exactly one wave per SIMD and read 1.00)."""
     rec = None
     with open(sweep_json) as fh:
         for line in fh:
@@ -316,7 +316,7 @@ def summarize_long_counters(pmc_csv, sweep_json, out_path, commands):
     by = {}
     with open(pmc_csv, newline="") as fh:
         for r in csv.DictReader(fh):
-            m = re.search(r"long_kernel<(float|double)>", r["Kernel_Name"])
+            m = re.search(r"long_kernel<(float|double), (?:true|false)>", r["Kernel_Name"])
             if not m:
                 continue
             d = by.setdefault(int(r["Dispatch_Id"]), dict(
@@ -325,17 +325,29 @@ def summarize_long_counters(pmc_csv, sweep_json, out_path, commands):
             d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
     disp = [by[i] for i in sorted(by)]
     # dispatches in sweep order: per length, the FP32 mode's passes, then the
-    # FP64 mode's; each pass launches both long kernels (the one of the other
-    # precision has no pairs), so per length and kernel the first passes are
-    # the FP32 mode's and the next the FP64 mode's
-    f32 = [d for d in disp if d["prec"] == "fp32"]
-    f64 = [d for d in disp if d["prec"] == "fp64"]
+    # FP64 mode's; each pass launches the lean and the general long kernel of
+    # both precisions (those of the other precision have no pairs), so per
+    # length and precision the first passes are the FP32 mode's and the next
+    # the FP64 mode's; a pass's lean and general dispatch are summed
+
+    def per_pass(ds):
+        out = []
+        for k in range(0, len(ds) - 1, 2):
+            a, b = ds[k], ds[k + 1]
+            d = {c: a.get(c, 0.0) + b.get(c, 0.0) for c in set(a) | set(b) if c != "prec"}
+            d["prec"] = a["prec"]
+            out.append(d)
+        return out
+    f32 = per_pass([d for d in disp if d["prec"] == "fp32"])
+    f64 = per_pass([d for d in disp if d["prec"] == "fp64"])
     lines = ["# Instruction counts of the long-pair kernels, equal-length pairs", "",
              "Commands (repository root, one MI355X):", ""]
     lines += ["    " + c for c in commands]
     lines += ["", "Workload: the length sweep's batches (one read of L bases against 16 haplotypes"
-              " of L bases per region); counters per pass of `long_kernel<float>` (FP32 mode) and"
-              " `long_kernel<double>` (FP64 mode), averaged over the passes of the run.", "",
+              " of L bases per region); counters per pass of `long_kernel<float, *>` (FP32 mode) and"
+              " `long_kernel<double, *>` (FP64 mode), the lean and the general kernel of the"
+              " precision summed (the sweep's reads have one gap byte: all pairs run in the lean"
+              " kernel), averaged over the passes of the run.", "",
               "| L | kernel | pairs | tiles/pair | ms | GCUPS | VALU per cell | SALU per cell |"
               " LDS per cell | VALU per CU-clock | waves per SIMD | wait share | clock GHz |",
               "|---:|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
