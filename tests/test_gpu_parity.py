@@ -236,6 +236,75 @@ def test_edge_cases(ctx32, ctx64):
         check(b, out, fl, plain64=plain)
 
 
+def _both_precisions(ctx32, ctx64, b):
+    for c, plain in ((ctx64, True), (ctx32, False)):
+        out, fl = phmm.phmm_forward_batch(c, b)
+        want, d = check(b, out, fl, plain64=plain)
+    return want, out, fl
+
+
+def test_n_bases_in_workload_regions(ctx32, ctx64):
+    """'N' matches any base (the reading of eq.3's match condition): regions
+    of the batched workload with 3% of the read and haplotype bases set to
+    'N', one read and one haplotype all 'N'; both precisions against the
+    oracle."""
+    b = synth.generate("batched_uneven", 23, 4)
+    rng = np.random.default_rng(23)
+    for key in ("reads", "haplotypes"):
+        a = b[key].copy()
+        a[rng.random(len(a)) < 0.03] = ord("N")
+        off = b["read_offsets" if key == "reads" else "hap_offsets"].astype(np.int64)
+        a[off[1]:off[2]] = ord("N")
+        b[key] = a
+    want, out, fl = _both_precisions(ctx32, ctx64, b)
+    say("N bases: %d pairs, log10 L %.2f .. %.2f" % (len(out), want.min(), want.max()))
+
+
+def test_one_base_sequences_among_ordinary_pairs(ctx32, ctx64):
+    """One-base haplotypes (one lane holding one real column), one-base reads
+    (the first row is the last) and two- and three-base ones, packed among
+    ordinary pairs of the same reads."""
+    rng = np.random.default_rng(31)
+    pairs = []
+    for _ in range(6):
+        hap = rnd(rng, int(rng.integers(150, 400)))
+        rd = hap[20:20 + int(rng.integers(90, 130))]
+        for h in (hap, hap[:1], hap[5:7], rnd(rng, 3), hap[1:200]):
+            pairs.append((rd, h, 30, 45, 45, 10))
+        for r in (rd[:1], rd[:2], rd[:3]):
+            pairs.append((r, hap, 25, 45, 45, 10))
+            pairs.append((r, hap[:1], 25, 45, 45, 10))
+    b = make_batch(pairs)
+    _both_precisions(ctx32, ctx64, b)
+
+
+def test_zero_likelihood_and_phred_extremes(ctx32, ctx64):
+    """A read whose first gap byte is 0 has T_DM = 0 on its first row, so
+    the paths that start in the delete row never reach a match: L = 0
+    exactly, -inf on both sides (FP32 rejects, FP64 hands it to the long
+    kernel).  Reads with every quality byte 0 (p_match = 0, T_MM clamped to
+    0) and every byte 255, among ordinary pairs; haplotypes of exactly
+    64 x 4 and 64 x 24 columns."""
+    rng = np.random.default_rng(37)
+    src = rnd(rng, 4000)
+    rd = src[300:430]
+    n = len(rd)
+    gq0 = np.full(n, 10)
+    gq0[0] = 0
+    pairs = [
+        (rd, src[250:250 + 300], 30, 45, 45, gq0),                 # L = 0
+        (rd, src[250:250 + 300], 0, 0, 0, 0),                      # every byte 0
+        (rd, src[250:250 + 300], 255, 255, 255, 255),              # every byte 255
+        (rd, src[200:200 + 64 * 4], 30, 45, 45, 10),               # 256 columns
+        (rd, src[200:200 + 64 * 24], 30, 45, 45, 10),              # 1536 columns
+        (rd, src[280:280 + 200], rng.integers(5, 41, n), 45, 45, 10),
+    ]
+    b = make_batch(pairs)
+    want, out, fl = _both_precisions(ctx32, ctx64, b)
+    assert not np.isfinite(want[0]) and not np.isfinite(out[0])
+    say("L = 0 pair: flags %d; log10 L of the others %s" % (fl[0], np.round(want[1:], 2)))
+
+
 def test_fp32_rescaled_windows_long_reads():
     """Reads of 768-1500 rows with haplotypes that fit a wavefront: the FP32
     kernels rescale the pack at 64-row windows, so sums far below the fixed
