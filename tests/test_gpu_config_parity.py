@@ -1,0 +1,106 @@
+"""Parity of whole workloads against the oracle, element by element: every
+pair of the batched uneven short-pair workload (20,000 regions, about 4.0e6
+pairs, 1.9e11 cells) and every pair of 10,000 regions of the genome-scale
+workload drawn at random (about 3.6e6 pairs, 2.0e11 cells).  The oracle is
+single-threaded C; its calls release the GIL, so host threads (one per
+logical CPU, at most 16) run it on chunks of the pairs in parallel.
+
+Tolerances as in test_gpu_parity: FP32-accepted results within 1e-4 in
+log10 L, FP64 results (reruns) within 1e-10; every pair carries exactly one
+precision flag, and the FP32 acceptance rule holds outside +-1e-3 of the
+threshold for reads of at most 256 rows."""
+import concurrent.futures as cf
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import paper_2606_25738_amd as phmm  # noqa: E402
+import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-4
+TOL64 = 1e-10
+THRESH = -28.0 - 120 * math.log10(2.0)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def oracle_all(b):
+    n = len(b["pair_list"])
+    threads = min(16, os.cpu_count() or 1)
+    chunks = np.array_split(np.arange(n), threads * 8)
+    with cf.ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda idx: oracle.forward_pairs(b, idx, rescale=True), chunks))
+    return np.concatenate(parts)
+
+
+def compare_all(b, out, fl, name):
+    want = oracle_all(b)
+    assert np.array_equal(np.isfinite(out), np.isfinite(want))
+    fin = np.isfinite(want)
+    d = np.where(fin, np.abs(np.where(fin, out, 0.0) - np.where(fin, want, 0.0)), 0.0)
+    is32 = (fl & phmm.PHMM_FLAG_FP32) != 0
+    is64 = (fl & phmm.PHMM_FLAG_FP64) != 0
+    assert np.all(is32 ^ is64)
+    say("%s: %d pairs, FP32 %d (max error %.2e), FP64 %d (max error %.2e), reruns %d"
+        % (name, len(out), is32.sum(), d[is32].max() if is32.any() else 0.0, is64.sum(),
+           d[is64].max() if is64.any() else 0.0, int(((fl & phmm.PHMM_FLAG_RERUN) != 0).sum())))
+    if is32.any():
+        assert d[is32].max() <= TOL32
+    if is64.any():
+        assert d[is64].max() <= TOL64
+    # acceptance rule for pairs that started in FP32 (reads of at most 256
+    # rows keep the fixed 2^120 scale): rerun iff log10 L is under the
+    # threshold, outside +-1e-3 of it
+    rerun = (fl & phmm.PHMM_FLAG_RERUN) != 0
+    started32 = is32 | rerun
+    rl = np.diff(b["read_offsets"].astype(np.int64))[b["pair_list"][:, 0].astype(np.int64)]
+    short = rl <= 256
+    assert not np.any(rerun & short & (want > THRESH + 1e-3))
+    assert np.all(rerun[started32 & short & (want < THRESH - 1e-3)])
+    return want, d
+
+
+def concat_batches(parts):
+    """One CSR batch from several (pair indices shifted by the reads and
+    haplotypes before them)."""
+    out = {k: np.concatenate([p[k] for p in parts]) for k in
+           ("reads", "base_quals", "ins_quals", "del_quals", "gcp", "haplotypes")}
+    ro, ho, pl = [np.zeros(1, np.uint64)], [np.zeros(1, np.uint64)], []
+    nr = nh = 0
+    for p in parts:
+        ro.append(p["read_offsets"][1:] + ro[-1][-1])
+        ho.append(p["hap_offsets"][1:] + ho[-1][-1])
+        pl.append(p["pair_list"].astype(np.uint32) + np.array([nr, nh], np.uint32))
+        nr += len(p["read_offsets"]) - 1
+        nh += len(p["hap_offsets"]) - 1
+    out["read_offsets"] = np.concatenate(ro)
+    out["hap_offsets"] = np.concatenate(ho)
+    out["pair_list"] = np.ascontiguousarray(np.concatenate(pl))
+    return out
+
+
+def test_batched_uneven_every_pair():
+    b = synth.generate("batched_uneven")
+    with phmm.Context() as c:
+        out, fl = phmm.phmm_forward_batch(c, b)
+    compare_all(b, out, fl, "batched uneven, 20,000 regions")
+
+
+def test_genome_scale_10k_random_regions_every_pair():
+    rng = np.random.default_rng(3)
+    starts = np.sort(rng.choice(1_000_000 // 500, size=20, replace=False)) * 500
+    b = concat_batches([synth.generate("genome_scale", int(s), 500) for s in starts])
+    with phmm.Context() as c:
+        out, fl = phmm.phmm_forward_batch(c, b)
+    compare_all(b, out, fl, "genome scale, 10,000 random regions")
