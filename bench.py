@@ -294,6 +294,63 @@ def summarize_counters(pmc_csv, bench_json, out_path, commands):
     print("\n".join(lines))
 
 
+LDS_COUNTERS = ("SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", "SQ_INSTS_VALU",
+                "SQ_BUSY_CU_CYCLES", "GRBM_GUI_ACTIVE")
+LDS_PROFILE = os.path.join(ROOT, "profiles", "lds_counters_short_fp32_wgs.md")
+
+
+def summarize_lds(pmc_csv, bench_json, out_path, commands):
+    """Writes the LDS profile of the FP32 short kernels from one rocprofv3
+    --pmc run with LDS_COUNTERS: LDS instructions per cell, bank-conflict
+    cycles (SQ_LDS_BANK_CONFLICT, summed over the shader engines) per LDS
+    instruction and as a share of the cycles the LDS was busy with indexed
+    operations (SQ_LDS_IDX_ACTIVE), per class and over the pass."""
+    rec = None
+    with open(bench_json) as fh:
+        for line in fh:
+            if line.startswith("{"):
+                rec = json.loads(line)
+    if rec is None:
+        raise SystemExit("no JSON line in %s" % bench_json)
+    cells = int(rec["config"]["cells"])
+    rows = _step_dispatches(pmc_csv)
+    tot = {c: sum(d.get(c, 0.0) for d in rows) for c in LDS_COUNTERS}
+    fast = [d for d in rows if d["kind"] == 0]
+    lines = ["# LDS counters of the FP32 short-pair kernels, genome-scale WGS-like batch", "",
+             "Commands (repository root, one MI355X):", ""]
+    lines += ["    " + c for c in commands]
+    lines += ["", "Workload: %d regions, %d pairs, %.6g cells; one forward pass (42 launches of"
+              " `short_kernel<float, c, kind>`; the table shows the fast kernel of each class, the"
+              " totals include the general ones). SQ counters summed over the shader engines;"
+              " LDS instructions are wave-instructions (x 64 for lane counts)."
+              % (rec["config"]["regions"], rec["config"]["pairs"], cells), "",
+              "| class c (N = 4 + c) | ms | LDS instructions | LDS per 100 VALU | bank-conflict cycles |"
+              " conflict cycles per LDS instruction | conflict share of LDS-busy cycles |",
+              "|---:|---:|---:|---:|---:|---:|---:|"]
+    for d in fast:
+        lds = d.get("SQ_INSTS_LDS", 0.0)
+        bc = d.get("SQ_LDS_BANK_CONFLICT", 0.0)
+        act = d.get("SQ_LDS_IDX_ACTIVE", 0.0)
+        lines.append("| %d | %.2f | %.4g | %.2f | %.4g | %.3f | %.4f |" % (
+            d["cls"], d["ns"] / 1e6, lds, 100.0 * lds / max(1.0, d.get("SQ_INSTS_VALU", 0.0)), bc,
+            bc / max(1.0, lds), bc / max(1.0, act)))
+    lines += ["", "Over the pass:", "",
+              "- lds_lane_instructions_per_cell: %.4f" % (64.0 * tot["SQ_INSTS_LDS"] / cells),
+              "- lds_per_100_valu: %.3f" % (100.0 * tot["SQ_INSTS_LDS"] / max(1.0, tot["SQ_INSTS_VALU"])),
+              "- bank_conflict_cycles_per_lds_instruction: %.4f"
+              % (tot["SQ_LDS_BANK_CONFLICT"] / max(1.0, tot["SQ_INSTS_LDS"])),
+              "- bank_conflict_share_of_lds_busy_cycles: %.5f"
+              % (tot["SQ_LDS_BANK_CONFLICT"] / max(1.0, tot["SQ_LDS_IDX_ACTIVE"])),
+              "- lds_busy_cycles_per_cu_busy_cycle: %.5f"
+              % (tot["SQ_LDS_IDX_ACTIVE"] / max(1.0, tot["SQ_BUSY_CU_CYCLES"])),
+              "- bank_conflict_cycles_per_cu_busy_cycle: %.6f"
+              % (tot["SQ_LDS_BANK_CONFLICT"] / max(1.0, tot["SQ_BUSY_CU_CYCLES"])),
+              "- sources_sha256: %s" % sources_digest(), ""]
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 LONG_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_WAVES", "SQ_WAVE_CYCLES",
                  "SQ_BUSY_CU_CYCLES", "SQ_WAIT_ANY", "GRBM_GUI_ACTIVE")
 LONG_COUNTERS_PROFILE = os.path.join(ROOT, "profiles", "long_kernels_counters.md")
@@ -970,6 +1027,8 @@ def main():
                     help="calls timed in the small-batch leg (0 = skip it in the default run)")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic profile from two rocprofv3 --pmc runs (no GPU used)")
+    ap.add_argument("--summarize-lds", nargs=2, metavar=("PMC_CSV", "BENCH_JSON"),
+                    help="write the LDS profile from a rocprofv3 --pmc run with the LDS counters")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("PMC_CSV", "BENCH_JSON"),
                     help="write the VALU counter profile from a rocprofv3 --pmc run with "
                          + " ".join(VALU_COUNTERS) + " and its bench.py output (no GPU used)")
@@ -986,6 +1045,9 @@ def main():
     if args.summarize_counters:
         summarize_counters(args.summarize_counters[0], args.summarize_counters[1], COUNTERS_PROFILE,
                            args.command)
+        return
+    if args.summarize_lds:
+        summarize_lds(args.summarize_lds[0], args.summarize_lds[1], LDS_PROFILE, args.command)
         return
     if args.summarize_long_counters:
         summarize_long_counters(args.summarize_long_counters[0], args.summarize_long_counters[1],
