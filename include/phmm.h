@@ -216,7 +216,9 @@ int phmm_forward_one(const uint8_t* read, const uint8_t* base_quals,
 
 /* Device-resident batch: the fields of phmm_forward_batch as device
  * pointers, plus bounds the caller guarantees (used to size the workspace
- * and to route pairs; they are not re-checked on the device). */
+ * and to route pairs; the device checks only that no haplotype is longer
+ * than 64 x 24 bases when max_hap_len says none is, see
+ * phmm_forward_batch_async). */
 typedef struct phmm_device_batch {
     const uint8_t* reads;
     const uint8_t* base_quals;
@@ -306,7 +308,9 @@ int phmm_forward_batch_noalloc(phmm_ctx* ctx, const phmm_device_batch* b, double
                                uint8_t* d_flags, void* hip_stream);
 
 /* Synchronises with the stream of the last async call and returns PHMM_OK or
- * the error the device recorded for it (PHMM_ETIMEOUT). */
+ * the error the device recorded for it: PHMM_ETIMEOUT (long-pair watchdog)
+ * or PHMM_ERANGE (a haplotype over 64 x 24 bases in a batch whose
+ * max_hap_len is at most that). */
 int phmm_device_status(phmm_ctx* ctx, void* d_workspace);
 
 /* Counters of the last call on a workspace (synchronises the stream). */
