@@ -235,12 +235,12 @@ __device__ __forceinline__ const double* long_pow<double>(const Tables& t, int g
     return t.pw64 + ((size_t)LongGeom<double>::cls * 256 + gcp) * kPowStride;
 }
 
-// Waves per SIMD the kernels are compiled for.  FP32: at 3 (168 VGPRs) the
-// row loops still keep every value in registers and the long pairs run
-// 20-24% faster than at the compiler's own choice of 2; at 4 the row loops
-// spill.  FP64: the lean kernel (no per-row gap changes, scaled form only)
-// runs at 2 (1.4-1.8x the general kernel's rate on 4-16 kbp pairs), the
-// general one keeps the compiler's choice of 1.
+// Waves per SIMD the kernels are compiled for.  FP32 lean: 4 (128 VGPRs;
+// the window records in LDS, spills only per tile), 6-9% faster than at 3
+// where its tiles fill the chip.  FP32 general: 3 (168 VGPRs; at 4 its row
+// loops spill), 20-24% faster than at the compiler's own choice of 2.  FP64
+// lean: 2 (1.4-1.8x the general kernel's rate on 4-16 kbp pairs); FP64
+// general: the compiler's choice of 1.
 template <typename R, bool GENERAL>
 constexpr int long_waves() { return sizeof(R) == 4 ? (GENERAL ? 3 : 4) : (GENERAL ? 1 : 2); }
 
