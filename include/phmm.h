@@ -107,7 +107,11 @@ typedef struct phmm_options {
     uint32_t long_fp32_max_rows; /* long pairs (haplotype > 64 x 24) with reads up to
                                this many rows run in FP32 with rescaling, longer ones
                                in FP64; default PHMM_MAX_READ (every long pair in
-                               FP32).  The per-row coefficients are rounded to FP32
+                               FP32).  A read with a gap byte above 10 on some row
+                               runs its long pairs in FP64 whatever its length: a
+                               long pair has no acceptance test, and with costly
+                               gaps the diagonals of a read unrelated to its
+                               haplotype drift further apart than FP32's range.  The per-row coefficients are rounded to FP32
                                stochastically (unbiased, keyed by the row) and each
                                cell adds its gap terms before its match term, so
                                rounding errors do not add up coherently along the

@@ -177,10 +177,33 @@ __device__ __forceinline__ int read_needs_general(const Batch& b, uint64_t roff,
     return (bad_g | bad_i) != 0u;
 }
 
+// Whether a read has a gap byte above kLongFp32MaxGap on some row.  A long
+// pair has no FP32 acceptance test: its rescaled FP32 sum is accepted
+// whatever its value.  FP32 keeps 2^126 between a tile's largest value and
+// the smallest it can hold; when gaps are costly (T_II = T_DD = 10^-gcp/10
+// small), the diagonals of a read unrelated to its haplotype drift apart by
+// more than that, and a diagonal flushed to zero can later carry the sum:
+// unrelated pairs of 2-6 kbp were off by up to 1e-1 in log10 at gap byte 20
+// and up to 4e1 at 25 (-inf at 60), while every gap byte of 10 or less kept
+// them within 6e-6.  Such reads run their long pairs in FP64.
+constexpr int kLongFp32MaxGap = 10;
+
+template <int kLanes>
+__device__ __forceinline__ int read_gap_over(const Batch& b, uint64_t roff, uint32_t l, int sub)
+{
+    constexpr uint32_t kAdd = (127u - (uint32_t)kLongFp32MaxGap) * 0x01010101u;
+    return scan_bytes<kLanes>(
+               b.gq + roff, l, sub,
+               [](uint32_t w) { return (((w & 0x7f7f7f7fu) + kAdd) | w) & 0x80808080u; },
+               [](uint8_t x) { return (uint32_t)(x > kLongFp32MaxGap); }) != 0u;
+}
+
 // Routing of long pairs: one workgroup per pair queued by the count kernel
 // scans the pair's read and appends the pair to the lean or the general long
-// list of its precision.  A read is scanned once per long pair: at most its
-// length in bytes against at least kShortMaxCols cells per row of the pair.
+// list of its precision (an FP32 pair whose read has a gap byte above
+// kLongFp32MaxGap to the FP64 lists).  A read is scanned once per long pair:
+// at most its length in bytes against at least kShortMaxCols cells per row
+// of the pair.
 constexpr int kRouteBlock = 256;
 constexpr int kRouteGrid = 1024;
 
@@ -195,8 +218,9 @@ __global__ __launch_bounds__(kRouteBlock) void long_route_kernel(Batch b, Work w
             const uint64_t roff = b.read_off[r];
             const uint32_t l = (uint32_t)(b.read_off[r + 1] - roff);
             const int slow = __syncthreads_or(read_needs_general<kRouteBlock>(b, roff, l, t));
+            const int wide = prec == 0 ? __syncthreads_or(read_gap_over<kRouteBlock>(b, roff, l, t)) : 1;
             if (t == 0) {
-                const int q = long_list_of(prec, slow != 0);
+                const int q = long_list_of(wide ? 1 : 0, slow != 0);
                 const uint32_t idx = atomicAdd(&w.ctr->n_long[q], 1u);
                 w.long_list[q][idx] = pair;
             }

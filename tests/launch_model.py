@@ -28,6 +28,7 @@ SMALL_BATCH_PAIRS = 8192
 SC_MAX_INS_Q = 65
 RING = 512
 LONG_TILE = 16 * WAVE
+LONG_FP32_MAX_GAP = 10  # FP32 long pairs need every gap byte at most this
 KMER_BASES = 32
 
 
@@ -273,11 +274,14 @@ class LaunchModel:
     def route(self):
         """The routing kernel: each pending long pair goes to the lean list
         of its precision when its read has one gap byte (>= 1) and insertion
-        bytes the scaled row form allows, else to the general one."""
+        bytes the scaled row form allows, else to the general one; an FP32
+        pair whose read has a gap byte above 10 goes to the FP64 lists."""
         for prec in (0, 1):
             for q in self.long_pend[prec]:
                 varying, sc_ok = self._read_profile(q)
-                lq = 2 * prec + (0 if (sc_ok and not varying) else 1)
+                r = self.pl[q, 0]
+                wide = prec == 1 or bool((self.b["gcp"][self.ro[r]:self.ro[r + 1]] > LONG_FP32_MAX_GAP).any())
+                lq = 2 * (1 if wide else 0) + (0 if (sc_ok and not varying) else 1)
                 self.long_list[lq].append(q)
                 need(len(self.long_list[lq]) <= self.cap, "long list overflow")
 

@@ -469,6 +469,35 @@ def test_long_pairs_lean_and_general_kernels(ctx32, ctx64):
         say("lean/general long pairs: flags %s, errors %s" % (list(fl), d))
 
 
+def test_long_pairs_costly_gaps_run_in_fp64(ctx32):
+    """A long pair has no FP32 acceptance test, and FP32's range cannot hold
+    the drift between the diagonals of a read unrelated to its haplotype when
+    gaps are costly; reads with a gap byte above 10 therefore run their long
+    pairs in FP64 (within 1e-10), the others in FP32 (within 1e-4), including
+    unrelated pairs of up to 20 kbp and high base qualities."""
+    rng = np.random.default_rng(46)
+    pairs, expect64 = [], []
+    for L, q, g in ((2000, 41, 10), (6000, 93, 10), (20000, 41, 10), (3000, 93, 8),
+                    (2000, 41, 20), (6000, 93, 25), (3000, 41, 60)):
+        pairs.append((rnd(rng, L), rnd(rng, int(L * 1.1)), q, 45, 45, g))  # unrelated
+        expect64.append(g > 10)
+    src = rnd(rng, 4400)
+    rd = bytearray(src[100:4100])
+    for j in rng.integers(0, 4000, 80):
+        rd[j] = ord("ACGT"[int(rng.integers(0, 4))])
+    gq = np.full(4000, 10)
+    gq[1234] = 30  # one costly row sends the read to FP64
+    pairs.append((bytes(rd), src, 30, 45, 45, gq))
+    expect64.append(True)
+    b = make_batch(pairs)
+    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    want, d = check(b, out, fl)
+    is64 = (fl & phmm.PHMM_FLAG_FP64) != 0
+    assert np.all(fl & phmm.PHMM_FLAG_LONG)
+    assert list(is64) == expect64
+    say("long pairs, costly gaps: flags %s, errors %s" % (list(fl), np.round(d, 9)))
+
+
 def test_fp64_underflow_goes_to_rescaled_kernel(ctx64):
     """A short pair whose FP64 scaled sum underflows (log10 L < -597) is
     recomputed by the rescaling kernel."""
