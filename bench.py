@@ -659,7 +659,9 @@ def sweep_leg(phmm, torch, args):
     """Length sweep of equal-length pairs (read and haplotypes of L bases,
     16 haplotypes per read), L = 32 ... 131072: kernel-only GCUPS (HIP events
     around the whole pass, packer included) in the default FP32 + rerun mode
-    and in plain FP64, best of `--sweep-reps` passes after one warm-up."""
+    and in plain FP64, best of `--sweep-reps` passes after one warm-up.  With
+    `--sweep-long-fp32` the FP32 mode also runs long pairs in the FP32 long
+    kernel (by default they run in FP64)."""
     rows = []
     for L in args.sweep_lengths or SWEEP_LENGTHS:
         regions = max(1, min(1_000_000, int(math.ceil(args.sweep_cells / (16.0 * L * L)))))
@@ -672,7 +674,9 @@ def sweep_leg(phmm, torch, args):
         res = {"length": L, "regions": regions, "pairs": n, "cells": cells}
         for mode, prec, peak in (("fp32", phmm.PHMM_FP32_RERUN, FP32_PEAK_TFLOPS),
                                  ("fp64", phmm.PHMM_FP64_PLAIN, FP32_PEAK_TFLOPS / 2)):
-            ctx = phmm.Context(precision=prec, timing=True)
+            opts = dict(long_fp32_max_rows=131072) if (args.sweep_long_fp32 and
+                                                        prec == phmm.PHMM_FP32_RERUN) else {}
+            ctx = phmm.Context(precision=prec, timing=True, **opts)
             ws = torch.empty(phmm.phmm_workspace_bytes(ctx, n, db.max_read_len, db.max_hap_len),
                              dtype=torch.uint8, device="cuda:0")
             stream = torch.cuda.Stream()
@@ -778,7 +782,10 @@ def long_reads_leg(phmm, torch, args):
     them and one per length class: kernel-only GCUPS (HIP events, best of
     `--long-reps` after a warm-up), the fraction of the vector roofline of
     the precision each class runs in, and every result's error against the
-    oracle values stored by tests/golden/make_long_reads_all.py."""
+    oracle values stored by tests/golden/make_long_reads_all.py.  Twice: with
+    the library's defaults (every long pair in the FP64 long kernel) and with
+    the FP32 long kernel enabled for every read length (long_fp32_max_rows =
+    PHMM_MAX_READ; exact enough on this workload, not for every input)."""
     with open(LONG_GOLDEN) as fh:
         gold = json.load(fh)["pairs"]
     want = np.array([float(g["log10_l"]) for g in gold])
@@ -786,14 +793,13 @@ def long_reads_leg(phmm, torch, args):
     cells_pp, rl, hl = pair_cells(b)
     assert np.array_equal(rl, [g["read_len"] for g in gold]) and \
         np.array_equal(hl, [g["hap_len"] for g in gold])
-    res = {"pairs": len(gold), "cells": int(cells_pp.sum())}
 
-    def one_pass(bb, cells):
+    def one_pass(bb, cells, opts):
         db = phmm.DeviceBatch(bb, "cuda:0")
         n = db.n_pairs
         out = torch.empty(n, dtype=torch.float64, device="cuda:0")
         fl = torch.empty(n, dtype=torch.uint8, device="cuda:0")
-        with phmm.Context(timing=True) as ctx:
+        with phmm.Context(timing=True, **opts) as ctx:
             ws = torch.empty(phmm.phmm_workspace_bytes(ctx, n, db.max_read_len, db.max_hap_len),
                              dtype=torch.uint8, device="cuda:0")
             stream = torch.cuda.Stream()
@@ -806,31 +812,37 @@ def long_reads_leg(phmm, torch, args):
             phmm.phmm_device_status(ctx, ws)
         return best, out.cpu().numpy(), fl.cpu().numpy()
 
-    ms, got, f = one_pass(b, res["cells"])
-    res["all"] = dict(ms=round(ms, 2), gcups=round(res["cells"] / ms / 1e6, 1))
-    classes = []
-    for L in (10000, 32000, 100000):
-        idx = np.nonzero(rl == L)[0]
-        sub = synth.subset_pairs(b, idx)
-        c = int(cells_pp[idx].sum())
-        cms, cgot, cf = one_pass(sub, c)
-        fp32 = bool(np.all(cf & 0x01))
-        peak = FP32_PEAK_TFLOPS if fp32 else FP32_PEAK_TFLOPS / 2
-        err = np.abs(got[idx] - want[idx])
-        classes.append(dict(read_len=L, pairs=len(idx), cells=c, ms=round(cms, 2),
-                            gcups=round(c / cms / 1e6, 1), precision="fp32" if fp32 else "fp64",
-                            roofline_frac=round(FLOPS_PER_CELL * c / (cms / 1e3) / (peak * 1e12), 4),
-                            max_err=float(err.max()), mean_err=float(err.mean()),
-                            bound=1e-4 if fp32 else 1e-10,
-                            ok=bool(err.max() <= (1e-4 if fp32 else 1e-10)),
-                            flags=sorted(set(int(x) for x in f[idx]))))
-        log("long reads %d bp: %d pairs, %.1f GCUPS (%s, %.1f%% of its roofline), max err %.3g"
-            % (L, len(idx), classes[-1]["gcups"], classes[-1]["precision"],
-               100 * classes[-1]["roofline_frac"], classes[-1]["max_err"]))
-    res["classes"] = classes
-    res["ok"] = all(c["ok"] for c in classes)
-    log("long-read workload: %d pairs, %.3g cells, %.1f GCUPS in one pass"
-        % (res["pairs"], res["cells"], res["all"]["gcups"]))
+    def run(opts, label):
+        res = {"pairs": len(gold), "cells": int(cells_pp.sum())}
+        ms, got, f = one_pass(b, res["cells"], opts)
+        res["all"] = dict(ms=round(ms, 2), gcups=round(res["cells"] / ms / 1e6, 1))
+        classes = []
+        for L in (10000, 32000, 100000):
+            idx = np.nonzero(rl == L)[0]
+            sub = synth.subset_pairs(b, idx)
+            c = int(cells_pp[idx].sum())
+            cms, cgot, cf = one_pass(sub, c, opts)
+            fp32 = bool(np.all(cf & 0x01))
+            peak = FP32_PEAK_TFLOPS if fp32 else FP32_PEAK_TFLOPS / 2
+            err = np.abs(got[idx] - want[idx])
+            classes.append(dict(read_len=L, pairs=len(idx), cells=c, ms=round(cms, 2),
+                                gcups=round(c / cms / 1e6, 1), precision="fp32" if fp32 else "fp64",
+                                roofline_frac=round(FLOPS_PER_CELL * c / (cms / 1e3) / (peak * 1e12), 4),
+                                max_err=float(err.max()), mean_err=float(err.mean()),
+                                bound=1e-4 if fp32 else 1e-10,
+                                ok=bool(err.max() <= (1e-4 if fp32 else 1e-10)),
+                                flags=sorted(set(int(x) for x in f[idx]))))
+            log("long reads (%s) %d bp: %d pairs, %.1f GCUPS (%s, %.1f%% of its roofline), max err %.3g"
+                % (label, L, len(idx), classes[-1]["gcups"], classes[-1]["precision"],
+                   100 * classes[-1]["roofline_frac"], classes[-1]["max_err"]))
+        res["classes"] = classes
+        res["ok"] = all(c["ok"] for c in classes)
+        log("long-read workload (%s): %d pairs, %.3g cells, %.1f GCUPS in one pass"
+            % (label, res["pairs"], res["cells"], res["all"]["gcups"]))
+        return res
+
+    res = run({}, "defaults: FP64 long kernel")
+    res["fp32_long_kernel"] = run(dict(long_fp32_max_rows=131072), "FP32 long kernel enabled")
     torch.cuda.empty_cache()
     return res
 
@@ -1017,6 +1029,8 @@ def main():
     ap.add_argument("--sweep-cells", type=float, default=1e11,
                     help="cells per length in the sweep (capped at 1,000,000 regions)")
     ap.add_argument("--sweep-reps", type=int, default=3)
+    ap.add_argument("--sweep-long-fp32", action="store_true",
+                    help="sweep: FP32 mode runs long pairs in the FP32 long kernel")
     ap.add_argument("--sweep-lengths", type=lambda v: [int(x) for x in v.split(",")], default=None,
                     help="comma-separated lengths of the sweep (default: 32 ... 131072)")
     ap.add_argument("--summarize-long-counters", nargs=2, metavar=("PMC_CSV", "SWEEP_JSON"),
@@ -1077,7 +1091,7 @@ def main():
         import paper_2606_25738_amd as phmm
         rows = sweep_leg(phmm, torch, args)
         print(json.dumps({"sweep": rows, "unit": "GCUPS (kernel-only)", "data": "synthetic",
-                          "reps": args.sweep_reps,
+                          "reps": args.sweep_reps, "long_fp32": bool(args.sweep_long_fp32),
                           "workload": "equal-length pairs, 16 haplotypes per read"}))
         return
 

@@ -90,14 +90,14 @@ typedef struct phmm_options {
     int precision;          /* PHMM_FP32_RERUN (default) or PHMM_FP64_PLAIN          */
     double accept_min_sum;  /* FP32 acceptance threshold, in [1e-30, 3e38]; default
                                1e-28.  An FP32 result is accepted iff its scaled sum
-                               is finite, > 0 and >= accept_min_sum.  Reads of up to
-                               256 rows keep the fixed scale, S32 = L * 2^120 (1e-28:
-                               log10 L >= -64.12).  Longer reads are rescaled by an
-                               exact power of two 2^f at 64-row windows (f >= 33 each
-                               time), so S32 = L * 2^(120 + sum f) there and such
-                               reads are accepted further down; a pair of such a pack
-                               whose own values had fallen under 2^-100 at a rescale
-                               is rerun whatever its sum.  A threshold above 2^120
+                               S32 = L * 2^120 (a fixed scale on every row) is
+                               finite, > 0 and >= accept_min_sum (1e-28: log10 L >=
+                               -64.12); else the pair is recomputed in FP64.  The
+                               fixed scale bounds what FP32's range can lose: along
+                               a path the weight only falls, so a cell flushed under
+                               2^-149 costs the sum at most 2^-149, at most
+                               l*k*2^-149 in all, under 1e-5 of an accepted sum for
+                               pairs of up to 10^10 cells.  A threshold above 2^120
                                reruns every pair in FP64.                             */
     int force_class;        /* -1: the packer picks columns-per-lane per region;
                                >= 0: force this class index (see phmm_class_n)       */
@@ -105,17 +105,24 @@ typedef struct phmm_options {
     uint32_t fp32_max_rows; /* reads longer than this go straight to FP64 (FP32
                                rounding bias grows with the row count); default 2048 */
     uint32_t long_fp32_max_rows; /* long pairs (haplotype > 64 x 24) with reads up to
-                               this many rows run in FP32 with rescaling, longer ones
-                               in FP64; default PHMM_MAX_READ (every long pair in
-                               FP32).  A read with a gap byte above 10 on some row
-                               runs its long pairs in FP64 whatever its length: a
-                               long pair has no acceptance test, and with costly
-                               gaps the diagonals of a read unrelated to its
-                               haplotype drift further apart than FP32's range.  The per-row coefficients are rounded to FP32
-                               stochastically (unbiased, keyed by the row) and each
-                               cell adds its gap terms before its match term, so
-                               rounding errors do not add up coherently along the
-                               read: within 1e-4 in log10 up to the longest reads    */
+                               this many rows run in the FP32 long kernel, the others
+                               in the FP64 one; default 0: every long pair in FP64.
+                               The long kernels rescale every 8 rows, which no
+                               acceptance test can make safe in FP32 (its range holds
+                               2^126 below a tile's largest value, and a path that far
+                               under, flushed, can carry the sum later): unrelated
+                               read/haplotype pairs with costly gaps and reads with a
+                               deletion of about 40 bases or more against their
+                               haplotype were off by up to thousands of decades.
+                               Where neither occurs (reads sampled from their
+                               haplotype with small indels, gap bytes of 10 or less,
+                               as in the long-read workload) FP32 stays within 3e-5
+                               at 100 kbp; reads with a gap byte above 10 keep FP64
+                               whatever this limit.  The per-row coefficients are
+                               rounded to FP32 stochastically (unbiased, keyed by the
+                               row) and each cell adds its gap terms before its
+                               match term, so rounding errors do not add up along
+                               the read.                                              */
     uint32_t watchdog_spins;/* long kernel: polls of a neighbour tile before giving
                                up with PHMM_ETIMEOUT; 0 = default                     */
     int timing;             /* 1: record per-phase HIP events (phmm_last_timing)     */

@@ -46,16 +46,17 @@ struct ScaleOf<double> {
     static constexpr int exp = 1020;
 };
 
-// FP32 packs of reads over kRescaleMinRows rows: at every 64-row window the
-// pack's largest value is brought back to 2^96 when it has fallen below 2^64
-// (an exact power-of-two multiply, the exponent kept as an integer), so reads
-// of a thousand rows and more keep their sums inside FP32's range instead of
-// being rerun in FP64.
-// Only a maximum of at least 2^-60 is rescaled, and a pair whose own largest
-// value is below 2^-100 at that moment (its values near FP32's denormals,
-// where precision is lost) is sent to FP64 whatever its final sum.
-constexpr int kRescaleBelow = 64, kRescaleTo = 96, kRescaleFloor = -60, kPairFloor = -100;
-constexpr int kRescaleMinRows = 256;  // shorter reads keep the fixed scale
+// The FP32 kernels keep the fixed scale 2^120/k on every row, which is what
+// makes the acceptance test sound.  Along any path the weight only falls
+// (every transition and emission factor is at most 1), and the weight of
+// all continuations of a cell is at most 1, so a cell flushed below FP32's
+// smallest number (2^-149) takes at most 2^-149 from the scaled sum: with the
+// sum at least 1e-28 (2^-93) the l*k cells of a pair lose at most l*k*2^-56
+// of it.  Rescaling the rows (bringing a decayed maximum back up) would void
+// that bound: a path far under a row's maximum, flushed there, can carry the
+// sum later (a read with a 50-base deletion against its haplotype lost 2.2
+// decades in FP32 when 64-row windows were rescaled), so reads whose sum
+// falls under the threshold are rerun in FP64 instead.
 
 template <typename R>
 __device__ __forceinline__ const R* pow_table(const Tables& t, int cls, int gcp);
@@ -105,7 +106,6 @@ void short_kernel(Batch b, Tables t, Work w, Policy pol)
     __shared__ int rinfo[kWave];  // read-base class mask | gcp byte << 16
     __shared__ int sflag[kWave];
     __shared__ uint32_t srej;
-    __shared__ uint32_t sdamage;  // FP32: pair slots whose values neared the denormal range
     // per pair (lane q < pairs of the pack): first lane | lanes << 8, pair
     // index, bit in the pack mask; per lane: real columns; per lane: its sum
     __shared__ uint32_t pinfo[3][kWave];
@@ -241,8 +241,6 @@ void short_kernel(Batch b, Tables t, Work w, Policy pol)
 #pragma unroll
         for (int n = 0; n < N; ++n) { Ma[n] = (R)0; Ia[n] = (R)0; }
         R Mleft = (R)0, Ileft = (R)0, C = (R)0;
-        int fexp = 0;  // FP32: binary orders added by window rescaling
-        if (lane == 0) sdamage = 0u;
 
         // all rows of the pack; SC selects the scaled form of the rows
         auto run_rows = [&](auto sc_tag) {
@@ -276,37 +274,6 @@ void short_kernel(Batch b, Tables t, Work w, Policy pol)
                 C = seg_scan(notstart * dpp<kWaveShr1>(vsh), mul);
             };
             for (int i0 = 0; i0 < l; i0 += kWave) {
-                if constexpr (kFP32) {
-                    if (i0 > 0 && l > kRescaleMinRows) {  // window rescale (see kRescaleBelow)
-                        R mx = maxR(C, maxR(Mleft, Ileft));
-#pragma unroll
-                        for (int n = 0; n < N; ++n) mx = maxR(mx, maxR(Ma[n], Ia[n]));
-                        const int le = mx > (R)0 ? exponent_of(mx) : -1000;
-                        const int wmax = wave_max_int(le + 1024) - 1024;
-                        if (wmax < kRescaleBelow && wmax > kRescaleFloor) {
-                            sflag[lane] = le;
-                            __syncthreads();
-                            if (lane < nseg) {
-                                const uint32_t pi = pinfo[0][lane];
-                                const int first = (int)(pi & 0xffu), cnt = (int)(pi >> 8);
-                                int pmax = -1000;
-                                for (int q = 0; q < cnt; ++q) pmax = max(pmax, sflag[first + q]);
-                                if (pmax < kPairFloor) atomicOr(&sdamage, 1u << lane);
-                            }
-                            const int f = min(kRescaleTo - wmax, 127);
-                            const R fs = pow2<R>(f);
-#pragma unroll
-                            for (int n = 0; n < N; ++n) {
-                                Ma[n] *= fs;
-                                Ia[n] *= fs;
-                            }
-                            Mleft *= fs;
-                            Ileft *= fs;
-                            C *= fs;
-                            fexp += f;
-                        }
-                    }
-                }
                 __syncthreads();
                 {   // priors of rows i0 .. i0+63 (eq.3 and the transition priors)
                     const int i = i0 + lane;
@@ -364,10 +331,9 @@ void short_kernel(Batch b, Tables t, Work w, Policy pol)
             if (kFP32) {
                 // a sum of 0 is rejected whatever the threshold: L > 0 may
                 // have underflowed in FP32
-                reject = ((sdamage >> lane) & 1u) != 0u || !(S > 0.0) ||
-                         !(S >= (double)pol.accept_min_sum) || !(S < 3.0e38);
+                reject = !(S > 0.0) || !(S >= (double)pol.accept_min_sum) || !(S < 3.0e38);
                 if (!reject) {
-                    b.out[pair] = log10_scaled_f32((float)s, ScaleOf<R>::exp + fexp);
+                    b.out[pair] = log10_scaled_f32((float)s, ScaleOf<R>::exp);
                     if (b.flags) b.flags[pair] = 0x01;  // FP32 accepted
                 }
             } else {

@@ -53,7 +53,7 @@ def long_active_waves(tiles: int, g: int) -> int:
 
 class Policy:
     def __init__(self, precision=0, force_class=-1, one_pair_per_wave=False, fp32_max_rows=2048,
-                 long_fp32_max_rows=131072, route_diverse=True, cost=None):
+                 long_fp32_max_rows=0, route_diverse=True, cost=None):
         self.precision = precision
         self.force_class = force_class
         self.one_pair_per_wave = one_pair_per_wave

@@ -8,7 +8,7 @@ logical CPU, at most 16) run it on chunks of the pairs in parallel.
 Tolerances as in test_gpu_parity: FP32-accepted results within 1e-4 in
 log10 L, FP64 results (reruns) within 1e-10; every pair carries exactly one
 precision flag, and the FP32 acceptance rule holds outside +-1e-3 of the
-threshold for reads of at most 256 rows."""
+threshold."""
 import concurrent.futures as cf
 import math
 import os
@@ -59,15 +59,13 @@ def compare_all(b, out, fl, name):
         assert d[is32].max() <= TOL32
     if is64.any():
         assert d[is64].max() <= TOL64
-    # acceptance rule for pairs that started in FP32 (reads of at most 256
-    # rows keep the fixed 2^120 scale): rerun iff log10 L is under the
-    # threshold, outside +-1e-3 of it
+    # acceptance rule for pairs that started in FP32 (the FP32 kernels keep
+    # the fixed 2^120 scale): rerun iff log10 L is under the threshold,
+    # outside +-1e-3 of it
     rerun = (fl & phmm.PHMM_FLAG_RERUN) != 0
     started32 = is32 | rerun
-    rl = np.diff(b["read_offsets"].astype(np.int64))[b["pair_list"][:, 0].astype(np.int64)]
-    short = rl <= 256
-    assert not np.any(rerun & short & (want > THRESH + 1e-3))
-    assert np.all(rerun[started32 & short & (want < THRESH - 1e-3)])
+    assert not np.any(rerun & (want > THRESH + 1e-3))
+    assert np.all(rerun[started32 & (want < THRESH - 1e-3)])
     return want, d
 
 

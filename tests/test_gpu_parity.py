@@ -42,6 +42,15 @@ def ctx32():
     c.close()
 
 
+@pytest.fixture(scope="module")
+def ctx32long():
+    """FP32 mode with the FP32 long kernel enabled for every read length
+    (by default long pairs run in FP64)."""
+    c = phmm.Context(precision=phmm.PHMM_FP32_RERUN, long_fp32_max_rows=131072)
+    yield c
+    c.close()
+
+
 def say(*a):
     print(*a, flush=True)
 
@@ -86,11 +95,10 @@ def test_one_region_fp32_rerun_policy():
         out, fl = phmm.phmm_forward_batch(c, b)
     want, d = check(b, out, fl)
     rerun = (fl & phmm.PHMM_FLAG_RERUN) != 0
-    # reads of 100 rows keep the fixed scale 2^120 (window rescaling starts
-    # above 256 rows), so the acceptance rule is exact: a pair is rerun if and
-    # only if its scaled sum L * 2^120 is under 1e-28, i.e. log10 L under
-    # -64.1236, outside a band of +-1e-3 for FP32 rounding
-    assert int(np.diff(b["read_offsets"].astype(np.int64)).max()) <= 256
+    # the FP32 kernels keep the fixed scale 2^120, so the acceptance rule is
+    # exact: a pair is rerun if and only if its scaled sum L * 2^120 is under
+    # 1e-28, i.e. log10 L under -64.1236, outside a band of +-1e-3 for FP32
+    # rounding
     assert not np.any(rerun[want > THRESH + 1e-3])
     assert np.all(rerun[want < THRESH - 1e-3])
     assert (want < THRESH - 1e-3).sum() > 100
@@ -305,26 +313,36 @@ def test_zero_likelihood_and_phred_extremes(ctx32, ctx64):
     say("L = 0 pair: flags %d; log10 L of the others %s" % (fl[0], np.round(want[1:], 2)))
 
 
-def test_fp32_rescaled_windows_long_reads():
+def test_fp32_acceptance_on_long_short_reads():
     """Reads of 768-1500 rows with haplotypes that fit a wavefront: the FP32
-    kernels rescale the pack at 64-row windows, so sums far below the fixed
-    2^120 scale's threshold are still accepted in FP32 within the bound.  In
-    a pack whose other pair sinks toward FP32's denormals, that pair goes to
-    FP64."""
+    kernels keep the fixed scale 2^120/k on every row, so a pair is accepted
+    in FP32 exactly when log10 L >= -64.12 (outside +-1e-3) and rerun in FP64
+    otherwise, at any read length.  The last read carries a 50-base deletion
+    against its haplotype (the path that carries the sum runs far under each
+    row's best for a while): at the fixed scale it is exact whichever way the
+    threshold sends it; with rows rescaled to keep FP32 in range such reads
+    had been accepted up to 2 decades off."""
     rng = np.random.default_rng(41)
     pairs = []
-    for l in (1500, 1450, 1400, 1200):
+    for l in (1500, 1450, 1400, 1200, 900, 768):
         hap = rnd(rng, l)
         read = bytearray(hap)
         for j in rng.integers(0, l, l // 60):
             read[j] = ord("ACGT"[int(rng.integers(0, 4))])
         pairs.append((bytes(read), hap, rng.integers(10, 41, l), 45, 45, 10))
+    hap = rnd(rng, 370)
+    rd = bytearray(hap[10:160] + hap[210:360])  # 300 rows, 50 haplotype bases deleted
+    for j in rng.integers(0, 300, 3):
+        rd[j] = ord("ACGT"[int(rng.integers(0, 4))])
+    pairs.append((bytes(rd), hap, 30, 45, 45, 10))
     b = make_batch(pairs)
     with phmm.Context() as c:
         out, fl = phmm.phmm_forward_batch(c, b)
     want, d = check(b, out, fl)
-    say("rescaled FP32 long reads: log10 L %s, flags %s, errors %s" % (np.round(want, 2), list(fl), d))
-    assert np.all(fl & phmm.PHMM_FLAG_FP32) and (want < THRESH).sum() >= 3
+    rerun = (fl & phmm.PHMM_FLAG_RERUN) != 0
+    say("FP32 acceptance, reads of 300-1500 rows: log10 L %s, flags %s" % (np.round(want, 2), list(fl)))
+    assert not np.any(rerun[want > THRESH + 1e-3]) and np.all(rerun[want < THRESH - 1e-3])
+    assert (want > THRESH + 1e-3).sum() >= 2 and (want < THRESH - 1e-3).sum() >= 2
     # one pack, two pairs: the read's own haplotype and an unrelated one
     hap = rnd(rng, 768)
     read = bytearray(hap)
@@ -424,7 +442,7 @@ def test_long_pairs_fp32_within_row_limit():
     say("FP32 long errors:", d[:3])
 
 
-def test_long_pairs_band_crosses_tiles_low_gap_penalty(ctx32, ctx64):
+def test_long_pairs_band_crosses_tiles_low_gap_penalty(ctx32long, ctx64):
     """The alignment band crosses every tile boundary, with a small gap
     continuation penalty (T_DD near 1), so deletions that open at a tile's
     first column carry weight across the tile: both precisions."""
@@ -437,14 +455,14 @@ def test_long_pairs_band_crosses_tiles_low_gap_penalty(ctx32, ctx64):
             read[j] = ord("ACGT"[int(rng.integers(0, 4))])
         pairs.append((bytes(read), hap, rng.integers(10, 41, l), 40, 40, gcp))
     b = make_batch(pairs)
-    for ctx in (ctx32, ctx64):
+    for ctx in (ctx32long, ctx64):
         out, fl = phmm.phmm_forward_batch(ctx, b)
         assert np.all(fl & phmm.PHMM_FLAG_LONG)
         want, d = check(b, out, fl)
         say("band-crossing long pairs: flags %s, errors %s" % (list(fl), d))
 
 
-def test_long_pairs_lean_and_general_kernels(ctx32, ctx64):
+def test_long_pairs_lean_and_general_kernels(ctx32long, ctx64):
     """Long pairs of both routes in one batch and both precisions: reads with
     one gap byte and insertion bytes of at most 65 run in the lean long
     kernel, reads with per-row gap bytes, an insertion byte above 65 or a gap
@@ -462,19 +480,20 @@ def test_long_pairs_lean_and_general_kernels(ctx32, ctx64):
             read[j] = ord("ACGT"[int(rng.integers(0, 4))])
         pairs.append((bytes(read), hap, rng.integers(10, 41, l), iq, 30, gq))
     b = make_batch(pairs)
-    for ctx in (ctx32, ctx64):
+    for ctx in (ctx32long, ctx64):
         out, fl = phmm.phmm_forward_batch(ctx, b)
         assert np.all(fl & phmm.PHMM_FLAG_LONG)
         want, d = check(b, out, fl)
         say("lean/general long pairs: flags %s, errors %s" % (list(fl), d))
 
 
-def test_long_pairs_costly_gaps_run_in_fp64(ctx32):
-    """A long pair has no FP32 acceptance test, and FP32's range cannot hold
-    the drift between the diagonals of a read unrelated to its haplotype when
-    gaps are costly; reads with a gap byte above 10 therefore run their long
-    pairs in FP64 (within 1e-10), the others in FP32 (within 1e-4), including
-    unrelated pairs of up to 20 kbp and high base qualities."""
+def test_long_pairs_costly_gaps_run_in_fp64(ctx32long):
+    """With the FP32 long kernel enabled: a long pair has no FP32 acceptance
+    test, and FP32's range cannot hold the drift between the diagonals of a
+    read unrelated to its haplotype when gaps are costly; reads with a gap
+    byte above 10 therefore still run their long pairs in FP64 (within
+    1e-10), the others in FP32 (within 1e-4), including unrelated pairs of up
+    to 20 kbp and high base qualities."""
     rng = np.random.default_rng(46)
     pairs, expect64 = [], []
     for L, q, g in ((2000, 41, 10), (6000, 93, 10), (20000, 41, 10), (3000, 93, 8),
@@ -490,7 +509,7 @@ def test_long_pairs_costly_gaps_run_in_fp64(ctx32):
     pairs.append((bytes(rd), src, 30, 45, 45, gq))
     expect64.append(True)
     b = make_batch(pairs)
-    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    out, fl = phmm.phmm_forward_batch(ctx32long, b)
     want, d = check(b, out, fl)
     is64 = (fl & phmm.PHMM_FLAG_FP64) != 0
     assert np.all(fl & phmm.PHMM_FLAG_LONG)
@@ -512,8 +531,8 @@ def test_fp64_underflow_goes_to_rescaled_kernel(ctx64):
 
 def test_long_fp32_beyond_default_row_limit():
     """FP32 long pairs with dithered coefficient rounding, on reads of 10 and
-    32 kbp (above the default FP32 row limit): the error against the oracle
-    stays within the FP32 bound."""
+    32 kbp (the FP32 long kernel enabled up to 200,000 rows): the error
+    against the oracle stays within the FP32 bound."""
     b = synth.generate("long_reads", 0, 1)
     b32 = synth.generate("long_reads", 32, 1)
     with phmm.Context(long_fp32_max_rows=200000) as c:
@@ -548,12 +567,13 @@ def _golden_long(name):
 
 
 @pytest.mark.parametrize("name", ["long_read_100k", "max_read_131072"])
-def test_longest_reads_against_stored_oracle(ctx32, name):
+def test_longest_reads_against_stored_oracle(ctx32long, name):
     """The long-read workload's 100 kbp read (110 kbp haplotype) and a read at
     the maximum length, 131,072 bases (144,179-base haplotype): FP32 long
-    kernel with rescaling (the default for every long pair), and for the
-    100 kbp read also the FP64 long kernel, against oracle values stored by
-    tests/golden/make_long_reads.py (a minute or more of oracle time each)."""
+    kernel with rescaling (enabled for every read length), and for the
+    100 kbp read also the FP64 long kernel (the default), against oracle
+    values stored by tests/golden/make_long_reads.py (a minute or more of
+    oracle time each)."""
     g = _golden_long(name)
     if name == "long_read_100k":
         b = synth.generate("long_reads", g["region"], 1)
@@ -563,32 +583,38 @@ def test_longest_reads_against_stored_oracle(ctx32, name):
                                 hap_len_factor=1.1), g["region"], 1)
     assert int(b["read_offsets"][1]) == g["read_len"] and int(b["hap_offsets"][1]) == g["hap_len"]
     say("%s: read %d, haplotype %d" % (name, g["read_len"], g["hap_len"]))
-    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    out, fl = phmm.phmm_forward_batch(ctx32long, b)
     want = float(g["log10_l"])
     say("  FP32: log10 L = %.9f (oracle %.9f, error %.2e), flags 0x%02x"
         % (out[0], want, out[0] - want, fl[0]))
     assert fl[0] & phmm.PHMM_FLAG_LONG and fl[0] & phmm.PHMM_FLAG_FP32
     assert abs(out[0] - want) <= TOL32
     if name == "long_read_100k":
-        with phmm.Context(long_fp32_max_rows=32768) as c64:
+        with phmm.Context() as c64:
             out, fl = phmm.phmm_forward_batch(c64, b)
         say("  FP64: log10 L = %.9f, error %.2e" % (out[0], out[0] - want))
         assert fl[0] & phmm.PHMM_FLAG_LONG and fl[0] & phmm.PHMM_FLAG_FP64
         assert abs(out[0] - want) <= TOL64
 
 
-def test_long_read_workload_against_stored_oracle(ctx32):
+def test_long_read_workload_against_stored_oracle(ctx32, ctx32long):
     """All 96 pairs of the long-read workload (32 each of 10, 32 and 100 kbp
     reads against haplotypes 1.1 times as long) in one batch, each against
-    the oracle value stored by tests/golden/make_long_reads_all.py: FP32 long
-    kernel within 1e-4 on every pair."""
+    the oracle value stored by tests/golden/make_long_reads_all.py: with the
+    defaults every pair in the FP64 long kernel within 1e-10; with the FP32
+    long kernel enabled, within 1e-4."""
     import json
     with open(os.path.join(ROOT, "tests", "golden", "long_reads_all.json")) as fh:
         gold = json.load(fh)["pairs"]
     b = synth.generate("long_reads")
     assert [int(x) for x in np.diff(b["read_offsets"])] == [g["read_len"] for g in gold]
-    out, fl = phmm.phmm_forward_batch(ctx32, b)
     want = np.array([float(g["log10_l"]) for g in gold])
+    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    assert np.all(fl == (phmm.PHMM_FLAG_LONG | phmm.PHMM_FLAG_RESCALED | phmm.PHMM_FLAG_FP64))
+    d64 = np.abs(out - want)
+    say("long reads, defaults (FP64 long kernel): max error %.2e" % d64.max())
+    assert d64.max() <= TOL64
+    out, fl = phmm.phmm_forward_batch(ctx32long, b)
     d = np.abs(out - want)
     for c, L in enumerate((10000, 32000, 100000)):
         say("long reads %d bp: max error %.2e, mean %.2e" % (L, d[32 * c:32 * c + 32].max(),

@@ -82,7 +82,7 @@ def test_edge_batch_l_zero_path():
     m = LaunchModel(b, Policy(precision=0).for_batch(len(b["pair_list"]), 1537))
     flags = m.run(lambda q: want[q] >= THRESH32, lambda q: want[q] >= THRESH64)
     assert 10 in m.long_list[3] and flags[10] == 0x1c
-    assert flags[9] == 0x0d  # FP32 long pair
+    assert flags[9] == 0x1c  # long pairs run in FP64 by default
 
 
 @pytest.mark.parametrize("q", range(13))
@@ -123,13 +123,18 @@ def test_long_pair_beyond_stated_bound():
     error; its output is still written once."""
     b = long_batch([100, 1600, 200], read_len=90)
     for prec in (0, 1):
-        m = LaunchModel(b, Policy(precision=prec).for_batch(3, 1536))
+        pol = Policy(precision=prec, long_fp32_max_rows=131072)
+        m = LaunchModel(b, pol.for_batch(3, 1536))
         m.run(lambda q: True, lambda q: True)
         assert m.bound_error and m.long_list[3] == [1]
         assert not any(m.long_list[:3])
-        m = LaunchModel(b, Policy(precision=prec).for_batch(3, 1600))
+        m = LaunchModel(b, pol.for_batch(3, 1600))
         m.run(lambda q: True, lambda q: True)
         assert not m.bound_error and m.long_list[2 * prec] == [1]
+    # by default long pairs run in FP64
+    m = LaunchModel(b, Policy(precision=0).for_batch(3, 1600))
+    m.run(lambda q: True, lambda q: True)
+    assert m.long_list[2] == [1]
 
 
 def test_long_pipeline_slot_reuse():
