@@ -517,6 +517,34 @@ def test_long_pairs_costly_gaps_run_in_fp64(ctx32long):
     say("long pairs, costly gaps: flags %s, errors %s" % (list(fl), np.round(d, 9)))
 
 
+def test_long_reads_with_large_indels_default_fp64(ctx32):
+    """Long reads (3000 rows) carrying a deletion or an insertion of 45-300
+    bases against their haplotype: the path through the gap runs far under
+    the tile's best for many columns, which the rescaled FP32 long kernel
+    cannot hold (it flushed such paths and was off by up to thousands of
+    decades).  With the defaults every long pair runs in the FP64 long
+    kernel, within 1e-10 of the oracle."""
+    rng = np.random.default_rng(47)
+    pairs = []
+    for kind in ("del", "ins"):
+        for dlen in (45, 60, 100, 300):
+            hap = rnd(rng, 3400)
+            mid = 1650
+            if kind == "del":
+                rd = bytearray(hap[150:mid] + hap[mid + dlen:3150 + dlen])
+            else:
+                rd = bytearray(hap[150:mid] + rnd(rng, dlen) + hap[mid:3150 - dlen])
+            for j in rng.integers(0, len(rd), len(rd) // 100):
+                rd[j] = ord("ACGT"[int(rng.integers(0, 4))])
+            pairs.append((bytes(rd), hap, 30, 45, 45, 10))
+    b = make_batch(pairs)
+    out, fl = phmm.phmm_forward_batch(ctx32, b)
+    want, d = check(b, out, fl)
+    assert np.all(fl == (phmm.PHMM_FLAG_LONG | phmm.PHMM_FLAG_RESCALED | phmm.PHMM_FLAG_FP64))
+    assert d.max() <= TOL64
+    say("long reads with large indels: log10 L %s, max error %.2e" % (np.round(want, 1), d.max()))
+
+
 def test_fp64_underflow_goes_to_rescaled_kernel(ctx64):
     """A short pair whose FP64 scaled sum underflows (log10 L < -597) is
     recomputed by the rescaling kernel."""
