@@ -642,7 +642,58 @@ def pair_cells(batch):
     return rl[pl[:, 0]] * hl[pl[:, 1]], rl[pl[:, 0]], hl[pl[:, 1]]
 
 
-def time_steps(phmm, torch, ctx, db, out, fl, ws, stream, warmup, steps):
+class ClockSampler:
+    """Samples the GPU's current shader clock (the starred level of the
+    driver's pp_dpm_sclk table in sysfs) every `period` seconds on a thread,
+    between start() and stop(); summary() is None where the table cannot be
+    read."""
+
+    def __init__(self, period=0.25):
+        import glob
+        self.paths = sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk"))
+        self.period, self.samples, self._stop = period, [], None
+
+    def _read(self):
+        best = None
+        for p in self.paths:
+            try:
+                with open(p) as fh:
+                    for line in fh:
+                        if "*" in line:
+                            m = re.search(r"(\d+)\s*[Mm][Hh]z", line)
+                            if m:
+                                best = max(best or 0, int(m.group(1)))
+            except OSError:
+                pass
+        return best
+
+    def start(self):
+        import threading
+        self._stop = threading.Event()
+
+        def run():
+            while not self._stop.wait(self.period):
+                v = self._read()
+                if v:
+                    self.samples.append(v)
+        self._th = threading.Thread(target=run, daemon=True)
+        self._th.start()
+        return self
+
+    def stop(self):
+        self._stop.set()
+        self._th.join()
+
+    def summary(self):
+        if not self.samples:
+            return None
+        x = np.array(self.samples)
+        return dict(median=int(np.median(x)), min=int(x.min()), max=int(x.max()), samples=len(x),
+                    source="pp_dpm_sclk (current level), every %.2f s of the timed steps"
+                    % self.period)
+
+
+def time_steps(phmm, torch, ctx, db, out, fl, ws, stream, warmup, steps, per_step=None):
     for i in range(warmup):
         phmm.phmm_forward_batch_async(ctx, db, out, fl, ws, stream)
         stream.synchronize()
@@ -658,6 +709,8 @@ def time_steps(phmm, torch, ctx, db, out, fl, ws, stream, warmup, steps):
     elapsed = time.perf_counter() - t0
     phmm.phmm_device_status(ctx, ws)
     avg = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
+    if per_step is not None:
+        per_step.extend(p["total_ms"] for p in phases)
     return elapsed, avg
 
 
@@ -993,8 +1046,8 @@ def genotype_leg(phmm, torch, ctx, batch, out, stream, reps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--regions", type=int, default=1000000,
                     help="regions of the workload (default: all 1,000,000)")
     ap.add_argument("--cpu-regions", type=int, default=1500,
@@ -1181,7 +1234,13 @@ def main():
         copy_gbs = 2.0 * nb / (e0.elapsed_time(e1) * 1e-3) / 1e9
         del src, dst
         log("calibration copy: %d MiB, %.0f GB/s" % (args.calib_copy_mib, copy_gbs))
-    elapsed, ph = time_steps(phmm, torch, ctx, db, out, fl, ws, stream, args.warmup, args.steps)
+    step_ms = []
+    clock = ClockSampler().start()
+    try:
+        elapsed, ph = time_steps(phmm, torch, ctx, db, out, fl, ws, stream, args.warmup,
+                                 args.steps, step_ms)
+    finally:
+        clock.stop()
     counts = phmm.phmm_last_counts(ctx, ws)
     ms_per_step = elapsed * 1000.0 / args.steps
     value = cells / (elapsed / args.steps) / 1e9
@@ -1273,7 +1332,10 @@ def main():
 
     rec = dict(
         metric=METRIC, value=round(value, 2), unit="GCUPS", n_gpus=1, steps=args.steps,
-        warmup=args.warmup, ms_per_step=round(ms_per_step, 3), higher_is_better=True,
+        warmup=args.warmup, ms_per_step=round(ms_per_step, 3),
+        step_ms=dict(median=round(float(np.median(step_ms)), 3), min=round(min(step_ms), 3),
+                     max=round(max(step_ms), 3), source="HIP events around each timed pass"),
+        sclk_mhz=clock.summary(), higher_is_better=True,
         scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
         config=dict(workload="genome-scale synthetic WGS-like batch: %d regions of 150 bp reads, "
                              "2-16 variant haplotypes of 150-600 bp, lognormal(mean 40, sigma 1) "
