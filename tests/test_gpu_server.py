@@ -200,3 +200,31 @@ def test_lanes_have_their_own_queues(stream_regions):
         for r, (b, fb, _) in zip(regs, got):
             a, fa = phmm.phmm_forward_batch(ctx, r)
             compare(a, fa, b, fb, near=True)
+
+
+def test_budget_admission_splits_batches():
+    """Regions submitted faster than they run wait in the queue; a lane takes
+    them in order while its batch still fits its share of the HBM budget.
+    3200 regions of one 10 kbp read against one 11 kbp haplotype (the
+    long-read workload's shortest class, each submitted 100 times; about
+    60 KB each, 1.1e8 cells) go to one lane of 168 MiB, of which the long
+    kernels' rings take 128 MiB: they go out in several batches, some cut
+    short by the budget (the server's full-batch count), and every region's
+    results equal those of the region run alone."""
+    b = synth.generate("long_reads")
+    uniq = [synth.region_slice(b, i) for i in range(32)]
+    assert all(int(np.diff(r["read_offsets"]).max()) == 10000 for r in uniq)
+    with phmm.Context() as ctx:
+        alone = [phmm.phmm_forward_batch(ctx, r) for r in uniq]
+    with phmm.Server(lanes=1, long_lanes=0, hbm_budget_bytes=168 << 20) as srv:
+        st0 = srv.stats()
+        ts = [srv.submit(uniq[i % 32]) for i in range(3200)]
+        got = [srv.wait(t) for t in ts]
+        st = srv.stats()
+    nb = st["batches"] - st0["batches"]
+    nfull = st["full_batches"] - st0["full_batches"]
+    say("budget admission: 3200 regions in %d batches, %d cut short by the budget" % (nb, nfull))
+    assert nfull >= 1 and nb >= 3
+    for i, (o, fo, _) in enumerate(got):
+        a, fa = alone[i % 32]
+        compare(a, fa, o, fo)
