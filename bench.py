@@ -783,11 +783,37 @@ def _best_pass(phmm, torch, ctx, db, reps):
     return best, fl.cpu().numpy()
 
 
+def _best_graph(phmm, torch, ctx, db, reps):
+    """Best of `reps` replays of the pass from the context's captured HIP
+    graph after one warm-up (which captures it), timed by events around the
+    call on its stream."""
+    n = db.n_pairs
+    out = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    fl = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    ws = torch.empty(phmm.phmm_workspace_bytes(ctx, n, db.max_read_len, db.max_hap_len),
+                     dtype=torch.uint8, device="cuda:0")
+    stream = torch.cuda.Stream()
+    best = None
+    for r in range(1 + reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        phmm.phmm_forward_batch_graph(ctx, db, out, fl, ws, stream)
+        e1.record(stream)
+        stream.synchronize()
+        if r > 0:
+            t = e0.elapsed_time(e1)
+            best = t if best is None else min(best, t)
+    phmm.phmm_device_status(ctx, ws)
+    return best
+
+
 def batched_uneven_leg(phmm, torch, args):
     """The batched uneven short-pair workload (20,000 regions, 2-8 variant
     haplotypes of 150-600 bp, 100-150 bp reads) and its stress variant with
     i.i.d. haplotypes, in FP32 + rerun and in plain FP64: kernel-only GCUPS
-    and the share of pairs rerun in FP64."""
+    and the share of pairs rerun in FP64; the FP32 + rerun pass also replayed
+    from its captured HIP graph."""
     res = {}
     for name, cfg in (("variant_haplotypes", "batched_uneven"), ("iid_haplotypes", synth.iid_haps_cfg("batched_uneven"))):
         b = synth.generate(cfg)
@@ -800,6 +826,9 @@ def batched_uneven_leg(phmm, torch, args):
             r[mode] = dict(ms=round(ms, 3), gcups=round(cells / ms / 1e6, 1))
             if prec == phmm.PHMM_FP32_RERUN:
                 r["rerun_fraction"] = round(float(((f & 0x02) != 0).mean()), 4)
+                with phmm.Context(precision=prec) as gctx:
+                    gms = _best_graph(phmm, torch, gctx, db, args.small_reps // 10 or 1)
+                r["fp32_rerun_graph"] = dict(ms=round(gms, 3), gcups=round(cells / gms / 1e6, 1))
         r["speedup_fp32_rerun"] = round(r["fp64"]["ms"] / r["fp32_rerun"]["ms"], 3)
         log("batched uneven pairs (%s): %d pairs, %.3g cells; FP32+rerun %.1f GCUPS (rerun %.1f%%), "
             "FP64 %.1f GCUPS" % (name, r["pairs"], cells, r["fp32_rerun"]["gcups"],
