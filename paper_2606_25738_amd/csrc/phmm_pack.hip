@@ -185,10 +185,7 @@ __device__ __forceinline__ int read_needs_general(const Batch& b, uint64_t roff,
 // more than that, and a diagonal flushed to zero can later carry the sum:
 // unrelated pairs of 2-6 kbp were off by up to 1e-1 in log10 at gap byte 20
 // and up to 4e1 at 25 (-inf at 60), while every gap byte of 10 or less kept
-// them within 6e-6.  Such reads run their long pairs in FP64 even where the
-// caller has enabled the FP32 long kernel (by default every long pair is
-// FP64: a read with a large deletion against its haplotype defeats FP32's
-// range whatever its gaps cost).
+// them within 6e-6.  Such reads run their long pairs in FP64.
 constexpr int kLongFp32MaxGap = 10;
 
 template <int kLanes>
