@@ -102,8 +102,12 @@ typedef struct phmm_options {
     int force_class;        /* -1: the packer picks columns-per-lane per region;
                                >= 0: force this class index (see phmm_class_n)       */
     int one_pair_per_wave;  /* 1: no packing, every pair gets its own wavefront      */
-    uint32_t fp32_max_rows; /* reads longer than this go straight to FP64 (FP32
-                               rounding bias grows with the row count); default 2048 */
+    uint32_t fp32_max_rows; /* reads longer than this go straight to FP64; default
+                               1024.  At the fixed FP32 scale a read with about 1%
+                               errors falls under the acceptance threshold from
+                               about a thousand bases on (85% of such pairs at 1536
+                               bases), so their FP32 pass would be wasted; FP32
+                               rounding bias also grows with the row count.          */
     uint32_t long_fp32_max_rows; /* long pairs (haplotype > 64 x 24) with reads up to
                                this many rows run in the FP32 long kernel, the others
                                in the FP64 one; default 0: every long pair in FP64.

@@ -78,7 +78,7 @@ extern "C" void phmm_default_options(phmm_options* o)
     o->accept_min_sum = 1e-28;
     o->force_class = -1;
     o->one_pair_per_wave = 0;
-    o->fp32_max_rows = 2048;
+    o->fp32_max_rows = 1024;
     o->long_fp32_max_rows = 0;  // every long pair in FP64 (see phmm.h)
     o->watchdog_spins = 0;
     o->timing = 0;

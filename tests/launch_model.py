@@ -52,7 +52,7 @@ def long_active_waves(tiles: int, g: int) -> int:
 
 
 class Policy:
-    def __init__(self, precision=0, force_class=-1, one_pair_per_wave=False, fp32_max_rows=2048,
+    def __init__(self, precision=0, force_class=-1, one_pair_per_wave=False, fp32_max_rows=1024,
                  long_fp32_max_rows=0, route_diverse=True, cost=None):
         self.precision = precision
         self.force_class = force_class

@@ -52,7 +52,7 @@ def test_default_options():
     assert o.precision == phmm.PHMM_FP32_RERUN
     assert o.accept_min_sum == 1e-28
     assert o.force_class == -1 and o.one_pair_per_wave == 0
-    assert o.fp32_max_rows == 2048 and o.long_fp32_max_rows == 0 and o.timing == 0
+    assert o.fp32_max_rows == 1024 and o.long_fp32_max_rows == 0 and o.timing == 0
     assert o.route_diverse_fp64 == 1
 
 

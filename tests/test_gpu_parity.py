@@ -314,9 +314,11 @@ def test_zero_likelihood_and_phred_extremes(ctx32, ctx64):
 
 
 def test_fp32_acceptance_on_long_short_reads():
-    """Reads of 768-1500 rows with haplotypes that fit a wavefront: the FP32
-    kernels keep the fixed scale 2^120/k on every row, so a pair is accepted
-    in FP32 exactly when log10 L >= -64.12 (outside +-1e-3) and rerun in FP64
+    """Reads of 768-1500 rows with haplotypes that fit a wavefront, with the
+    FP32 row limit raised to 2048 (the default, 1024, sends the longer ones
+    straight to FP64, which the second call checks): the FP32 kernels keep
+    the fixed scale 2^120/k on every row, so a pair is accepted in FP32
+    exactly when log10 L >= -64.12 (outside +-1e-3) and rerun in FP64
     otherwise, at any read length.  The last read carries a 50-base deletion
     against its haplotype (the path that carries the sum runs far under each
     row's best for a while): at the fixed scale it is exact whichever way the
@@ -337,6 +339,11 @@ def test_fp32_acceptance_on_long_short_reads():
     pairs.append((bytes(rd), hap, 30, 45, 45, 10))
     b = make_batch(pairs)
     with phmm.Context() as c:
+        out, fl = phmm.phmm_forward_batch(c, b)
+    check(b, out, fl)
+    rows = np.diff(b["read_offsets"].astype(np.int64))
+    assert np.all(fl[rows > 1024] == phmm.PHMM_FLAG_FP64)
+    with phmm.Context(fp32_max_rows=2048) as c:
         out, fl = phmm.phmm_forward_batch(c, b)
     want, d = check(b, out, fl)
     rerun = (fl & phmm.PHMM_FLAG_RERUN) != 0
