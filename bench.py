@@ -813,7 +813,8 @@ def batched_uneven_leg(phmm, torch, args):
     haplotypes of 150-600 bp, 100-150 bp reads) and its stress variant with
     i.i.d. haplotypes, in FP32 + rerun and in plain FP64: kernel-only GCUPS
     and the share of pairs rerun in FP64; the FP32 + rerun pass also replayed
-    from its captured HIP graph."""
+    from its captured HIP graph, and both modes through the synchronous call
+    (device time of its pass)."""
     res = {}
     for name, cfg in (("variant_haplotypes", "batched_uneven"), ("iid_haplotypes", synth.iid_haps_cfg("batched_uneven"))):
         b = synth.generate(cfg)
@@ -830,6 +831,18 @@ def batched_uneven_leg(phmm, torch, args):
                     gms = _best_graph(phmm, torch, gctx, db, args.small_reps // 10 or 1)
                 r["fp32_rerun_graph"] = dict(ms=round(gms, 3), gcups=round(cells / gms / 1e6, 1))
         r["speedup_fp32_rerun"] = round(r["fp64"]["ms"] / r["fp32_rerun"]["ms"], 3)
+        # the synchronous call's pass (host arrays; device time from its HIP
+        # events), which launches only the kernels that have work
+        sync = {}
+        for mode, prec in (("fp32_rerun", phmm.PHMM_FP32_RERUN), ("fp64", phmm.PHMM_FP64_PLAIN)):
+            with phmm.Context(precision=prec, timing=True) as ctx:
+                ts = []
+                for rep in range(3):
+                    phmm.phmm_forward_batch(ctx, b)
+                    ts.append(phmm.phmm_last_timing(ctx)["total_ms"])
+            ms = min(ts[1:])
+            sync[mode] = dict(ms=round(ms, 3), gcups=round(cells / ms / 1e6, 1))
+        r["sync_pass"] = sync
         log("batched uneven pairs (%s): %d pairs, %.3g cells; FP32+rerun %.1f GCUPS (rerun %.1f%%), "
             "FP64 %.1f GCUPS" % (name, r["pairs"], cells, r["fp32_rerun"]["gcups"],
                                 100 * r["rerun_fraction"], r["fp64"]["gcups"]))
