@@ -491,6 +491,34 @@ def summarize_trace(trace_csv, bench_json, out_path, commands):
               "- trace_family_ms: %.3f" % (sum(timed) / len(timed)),
               "- events_family_ms: %.3f" % rec["roofline"]["kernel_ms"],
               "- sources_sha256: %s" % sources_digest(), ""]
+    # the plain FP64 passes of the same run (its fp64_plain leg): groups of
+    # 21 consecutive launches of short_kernel<double, c, 2>, the two with the
+    # largest total (the FP32 steps also launch them, for their few reruns)
+    calls64, cur = [], []
+    for r in rows:
+        m = re.search(r"short_kernel<double, (\d+), 2>", r["Kernel_Name"])
+        if not m:
+            continue
+        cur.append((int(m.group(1)), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
+        if len(cur) == N_CLASSES:
+            calls64.append(cur)
+            cur = []
+    if rec.get("fp64_plain") and len(calls64) >= 2:
+        tot64 = [sum(d for _, d in c) for c in calls64]
+        big64 = sorted(range(len(calls64)), key=lambda i: -tot64[i])[:2]
+        lines += ["## Plain FP64 passes of the same run", "",
+                  "Each of the two plain FP64 forward calls (`fp64_plain`: 1 warm-up + 1 timed) is 21"
+                  " launches of `short_kernel<double, c, 2>`; mean duration per class (the FP64"
+                  " kernels' occupancy targets: 1 wave per SIMD as the compiler chooses for"
+                  " N = 4-8, 3 for N = 9-15, 2 for N = 16-24; packed with the run's autotuned"
+                  " cost table, %s)." % ("N + %g" % (rec["pack_costs"]["fp64"][0] - 4)
+                                         if rec.get("pack_costs") else "the default"), "",
+                  "| class c (N = 4 + c) | ms |", "|---:|---:|"]
+        for c in range(N_CLASSES):
+            ds = [d for i in big64 for cc, d in calls64[i] if cc == c]
+            lines.append("| %d | %.2f |" % (c, sum(ds) / len(ds) / 1e3))
+        lines += ["", "- fp64_family_ms: %.3f" % (sum(tot64[i] for i in big64) / 2 / 1e3),
+                  "- fp64_plain_ms_per_step: %.3f" % rec["fp64_plain"]["ms_per_step"], ""]
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines))
     print("\n".join(lines))
