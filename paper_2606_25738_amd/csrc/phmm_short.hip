@@ -87,8 +87,9 @@ constexpr int waves_target()
                                              5, 5, 5, 5, 4, 4, 4, 4, 4, 4};
     // FP64: timed per class on the genome-scale batch in plain FP64 at 1
     // (the compiler's choice), 2, 3 and 4 waves; N = 4-8 gain nothing from a
-    // target, N = 9-15 run best at 3, N = 16-24 at 2 (1.45x faster than the
-    // one wave per SIMD that 256 VGPRs plus accumulation registers give)
+    // target, N = 9-15 run best at 3, N = 16-24 at 2 rather than the one wave
+    // per SIMD that 256 VGPRs plus accumulation registers give (the whole
+    // plain FP64 pass on that batch: 7.32 s before, 6.55-6.69 s after)
     constexpr int fp64_waves[kNumClasses] = {1, 1, 1, 1, 1, 3, 3, 3, 3, 3, 3,
                                              3, 2, 2, 2, 2, 2, 2, 2, 2, 2};
     return KIND == kFast32 ? fast_waves[CLS] : KIND == kAll64 ? fp64_waves[CLS] : 1;
