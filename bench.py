@@ -672,9 +672,9 @@ def pair_cells(batch):
 
 class ClockSampler:
     """Samples the GPU's current shader clock (the starred level of the
-    driver's pp_dpm_sclk table in sysfs) every `period` seconds on a thread,
-    between start() and stop(); summary() is None where the table cannot be
-    read."""
+    amdgpu kernel module's pp_dpm_sclk table in sysfs) every `period`
+    seconds on a thread, between start() and stop(); summary() is None where
+    the table cannot be read."""
 
     def __init__(self, period=0.25):
         import glob
